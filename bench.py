@@ -1,0 +1,139 @@
+"""Benchmark: GB/s of field corrected on one MI355X.
+
+Default workload: the plain correction of a 512^3 float32 turbulence-like
+field (Gaussian random field with P(k) ~ k^-11/3, seed 2) quantised by a
+Lorenzo predictor + bin-2*eps residual quantiser, eps = 1e-4 of the value
+range, 14-neighbour Freudenthal mesh, N = 5, reformulated event constraints.
+One step = one full exz_correct call (validation, reference topology, sorted
+critical points, loop to the fixpoint) from g_hat into a separate output,
+with f and g_hat already resident in HBM.
+
+Prints one JSON line.  ``roofline`` is for the dominant kernel (the dense
+check pass): algorithmic bytes per launch ((b + 1) bytes per vertex: the
+field value and the reference code byte) over its average launch time,
+measured with HIP events on the library's stream during the timed steps.
+``cpu_baseline`` is the CPU oracle, single thread, on a bounded sample of
+the same input (a 128^3 sub-block of the field, corrected to convergence).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(case, edge=128):
+    """Time the CPU oracle on an edge^3 sub-block of the workload."""
+    import numpy as np
+    import oracle
+
+    f = np.ascontiguousarray(case.f[:edge, :edge, :edge])
+    g = np.ascontiguousarray(case.g_hat[:edge, :edge, :edge])
+    oracle.lib()
+    t0 = time.perf_counter()
+    _, _, st, _ = oracle.correct(f, g, case.xi)
+    dt = time.perf_counter() - t0
+    return {"value": f.size * f.itemsize / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "%d^3 sub-block of the same field (1/%d of it), corrected to convergence "
+                      "(%d iterations) in %.1f s, one thread" % (edge, case.f.size // f.size,
+                                                                 st["iterations"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--edge", type=int, default=512, help="field edge (default 512)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--poll", type=int, default=0)
+    ap.add_argument("--tile-y", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2604_01397_amd import exactz, synth
+
+    t0 = time.time()
+    case = synth.config2(args.edge)
+    log("generated %s in %.1f s (xi=%g)" % (case.name, time.time() - t0, case.xi))
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(case.f).to(dev)
+    g = torch.from_numpy(case.g_hat).to(dev)
+    g_out = torch.empty_like(f)
+    cnt = torch.zeros(f.shape, dtype=torch.uint8, device=dev)
+    ctx = exactz.Context(0, profile=1, poll=args.poll, tile_y=args.tile_y)
+    stream = torch.cuda.current_stream()
+    res = None
+    for w in range(args.warmup):
+        _, _, res = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt)
+        log("warmup %d: %s" % (w, res))
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    check_ms, check_n = 0.0, 0
+    results = []
+    for k in range(args.steps):
+        _, _, res = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt, stream=stream)
+        check_ms += res["check_ms"]
+        check_n += res["check_launches"]
+        results.append(res)
+        log("step %d: iters=%d edited=%d status=%d setup=%.2f ms loop=%.2f ms" % (
+            k, res["iterations"], res["edited_vertices"], res["status"], res["setup_ms"],
+            res["loop_ms"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms = elapsed * 1e3 / args.steps
+    n = case.f.size
+    b = case.f.itemsize
+    value = n * b / (ms * 1e-3) / 1e9
+    avg_check_ms = check_ms / max(check_n, 1)
+    algo_bytes = (b + 1) * n
+    achieved = algo_bytes / (avg_check_ms * 1e-3) / 1e9
+    line = {
+        "metric": "GB/s of field corrected on 1 MI355X (plain)",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain correction, %d^3 float32 GRF k^-11/3 (seed 2), Lorenzo "
+                               "quantiser, eps = 1e-4 range, N = 5, reformulated" % args.edge,
+                   "n": n, "iterations": res["iterations"], "edited_vertices": res["edited_vertices"],
+                   "num_critical": res["num_critical"], "setup_ms": round(res["setup_ms"], 3),
+                   "loop_ms": round(res["loop_ms"], 3)},
+        "roofline": {"bound": "hbm", "kernel": "k_check", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_ms": round(avg_check_ms, 5),
+                     "launches": check_n, "bytes_per_launch": algo_bytes},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sub-block ...")
+        line["cpu_baseline"] = cpu_baseline(case)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

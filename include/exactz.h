@@ -1,0 +1,200 @@
+/* exactz.h -- C ABI of the MI355X (gfx950) EXaCTz correction library.
+ *
+ * The library corrects a decompressed scalar field g_hat against its
+ * original f so that the extremum graph and the contour tree of the result
+ * equal those of f, while every value stays within the absolute error bound
+ * xi (EXaCTz, arXiv 2604.01397).  It implements Algorithm 1 of the paper:
+ *   g <- g_hat; repeat { S <- CheckConstraints(g, f); stop if S is empty;
+ *                        g <- ApplyBoundedEdits(g, S, xi) }
+ * with the checks of Sec. 4.2 (steepest ascent / descent neighbours, saddle
+ * link order) and the event constraints either in the reformulated form of
+ * Sec. 4.3 (the order of all critical points of f) or in the original form
+ * of Sec. 4.2 (saddle order and per-saddle extremum selection traced along
+ * integral paths).  Edits follow Sec. 3.3: each round a flagged vertex drops
+ * by Delta = xi_T / N; the (N+1)-th edit stores the lower bound itself.
+ *
+ * Conventions shared by every entry point:
+ *  - Fields are dense arrays of float32 or float64 with x the fastest index:
+ *    vertex (x, y, z) is element x + nx*(y + ny*z).  dims[] holds
+ *    (nx, ny, nz); unused trailing dims are 1.  1D, 2D and 3D fields live on
+ *    the Freudenthal triangulation of the grid (14 neighbours in 3D, 6 in
+ *    2D, 2 in 1D).  Ties are broken by the linear index (Sec. 3.3, footnote).
+ *  - All field pointers are DEVICE pointers owned by the caller; the library
+ *    never frees caller memory.  f and g_hat are read-only; g_out may alias
+ *    g_hat (in-place correction).
+ *  - xi_T, the largest value of the field type not above xi, is the bound
+ *    actually enforced; L_i / U_i are the exact round-up of f_i - xi_T and
+ *    round-down of f_i + xi_T.  g_hat must satisfy L_i <= g_hat_i <= U_i.
+ *  - Work is issued on the given HIP stream (hipStream_t passed as void*;
+ *    NULL = the default stream).  Calls return after that stream has
+ *    finished the correction (the loop polls a device flag), so results are
+ *    valid on return.
+ *  - One context serves one host thread at a time; a reentrant call on a
+ *    busy context returns EXZ_E_BUSY.
+ *  - The result depends only on (f, g_hat, params): not on tile shapes,
+ *    batch composition, other jobs or the number of iterations per poll.
+ */
+#ifndef EXACTZ_H
+#define EXACTZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { EXZ_F32 = 0, EXZ_F64 = 1 } exz_dtype;
+
+typedef enum {
+  EXZ_EVENT_REFORMULATED = 0, /* order of all critical points (Sec. 4.3) */
+  EXZ_EVENT_ORIGINAL = 1      /* saddle order + path-traced selection (Sec. 4.2) */
+} exz_event_mode;
+
+typedef enum {
+  EXZ_OK = 0,
+  EXZ_W_STUCK = 1,      /* fixpoint with violations left: every target sits at
+                           its lower bound (float rounding made two distinct
+                           f values share one bound); residual_violations > 0 */
+  EXZ_W_MAX_ITERS = 2,  /* stopped after params.max_iters changing rounds */
+  EXZ_E_INVALID = -1,   /* null pointer, ndim not in 1..3, a dim < 1,
+                           n >= 2^31, xi not finite or xi_T <= 0, n_steps
+                           outside 1..14, unknown mode or dtype */
+  EXZ_E_NONFINITE = -2, /* NaN or Inf in f or g_hat */
+  EXZ_E_BOUND = -3,     /* some g_hat_i outside [L_i, U_i] */
+  EXZ_E_NOMEM = -4,     /* device or pinned allocation failed / over budget */
+  EXZ_E_HIP = -5,       /* a HIP runtime call failed (see exz_last_error) */
+  EXZ_E_BUSY = -6       /* context already in use */
+} exz_status;
+
+/* Problem description (Algorithm 1 inputs besides the two fields). */
+typedef struct {
+  int32_t ndim;        /* 1, 2 or 3 */
+  int32_t dtype;       /* exz_dtype */
+  int64_t dims[3];     /* nx, ny, nz; unused = 1 */
+  double xi;           /* absolute error bound, > 0 */
+  int32_t n_steps;     /* N of Sec. 3.3; 5 in the paper; 1..14 */
+  int32_t event_mode;  /* exz_event_mode */
+  int64_t max_iters;   /* 0 = run to the fixpoint */
+  int32_t certify;     /* 1 = after the loop, verify on the device that every
+                          vertex's steepest-descent and steepest-ascent path
+                          ends where it ends in f and that all critical types
+                          agree (the extremum-graph identity of Sec. 4.1) */
+  int32_t resume;      /* 1 = cnt_io holds edit counts of an earlier call on
+                          the same f (g_hat is then the state it left) */
+} exz_params;
+
+/* Outcome of one correction. */
+typedef struct {
+  int64_t iterations;          /* rounds that changed at least one value */
+  int64_t edited_vertices;     /* vertices whose count went 0 -> 1 in this call */
+  int64_t edit_ops;            /* value changes in this call (|E| increments) */
+  int64_t lossless_vertices;   /* vertices given the lower bound by the
+                                  (N+1)-th edit in this call */
+  int64_t floor_vertices;      /* vertices that reached L_i in this call */
+  int64_t residual_violations; /* |S| at a stuck fixpoint, else 0 */
+  int64_t num_critical;        /* critical points of f */
+  int32_t status;              /* exz_status of the call */
+  int32_t certified;           /* -1 not run, 0 mismatch, 1 identical */
+  double setup_ms;             /* device time of validation + reference topology */
+  double loop_ms;              /* device time of the correction loop */
+  int64_t check_launches;      /* profiling: check passes that did work */
+  double check_ms;             /* profiling: their summed device time */
+} exz_result;
+
+typedef struct exz_ctx exz_ctx;
+
+/* Create a context on HIP device `device` (makes it current on this
+ * thread).  The context owns a device workspace that grows on demand and is
+ * reused across calls.  *out is set on success. */
+exz_status exz_ctx_create(int device, exz_ctx **out);
+
+/* Release the context and its workspace.  NULL is accepted. */
+exz_status exz_ctx_destroy(exz_ctx *ctx);
+
+/* Tuning and diagnostics.  Keys:
+ *   "profile"  0/1: record device events around every check pass and
+ *              report check_launches / check_ms;
+ *   "poll"     iterations issued between two host polls (1..256; default:
+ *              adaptive, starting at 4);
+ *   "graph"    0/1: replay the iterations between polls from a captured
+ *              hipGraph (default 1);
+ *   "tile_y"   rows per check work-group (1, 2, 4, 8, 16; default 4).
+ * Returns EXZ_E_INVALID for an unknown key or value. */
+exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value);
+
+/* Device workspace the library needs for one field, in bytes, beyond the
+ * caller's f, g_hat, g_out and cnt_io.  Sizes the per-critical-point arrays
+ * for the worst case (every vertex critical).  0 for invalid params. */
+size_t exz_workspace_bytes(const exz_params *params);
+
+/* Correct one field (Algorithm 1).
+ *   f       device, n values of params->dtype, read-only
+ *   g_hat   device, n values, read-only unless aliased by g_out
+ *   g_out   device, n values, receives g'
+ *   cnt_io  device, n bytes, nullable: receives the per-vertex edit count
+ *           (the edit set E of Algorithm 1: 0..N+1); read first if
+ *           params->resume
+ *   result  host, filled on every return (status mirrors the return value)
+ *   stream  hipStream_t or NULL
+ * Errors: see exz_status.  On an error status g_out is unspecified. */
+exz_status exz_correct(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
+                       uint8_t *cnt_io, const exz_params *params, exz_result *result,
+                       void *stream);
+
+/* One field of a batch. */
+typedef struct {
+  exz_params params;
+  const void *f;      /* device */
+  const void *g_hat;  /* device */
+  void *g_out;        /* device, may alias g_hat */
+  uint8_t *cnt_io;    /* device, nullable */
+} exz_field;
+
+/* Correct many fields of mixed size, dimension and dtype together: each
+ * phase of an iteration is one launch over the (field, tile) items of all
+ * fields that have not converged, with per-field worklists, counters and
+ * convergence flags (Algorithm 1 run independently per field).  results[k]
+ * is what exz_correct would return for fields[k], bit for bit.  Returns the
+ * first error status among the fields, else EXZ_OK (warnings are per
+ * field). */
+exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfields,
+                             exz_result *results, void *stream);
+
+/* Serving primitives: a job keeps its correction state resident on the
+ * device between calls, so a host scheduler can admit new jobs while others
+ * iterate (continuous batching).  exz_job_create validates the field and
+ * builds the reference topology of f (it allocates the job's workspace);
+ * exz_step advances every listed unfinished job by up to `iters` rounds in
+ * shared batched launches; exz_job_poll reports completion; exz_job_release
+ * frees the job's workspace (not the caller's buffers).  A job's final
+ * state equals exz_correct on the same field. */
+typedef struct exz_job exz_job;
+exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, exz_job **out);
+exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t iters,
+                    void *stream);
+exz_status exz_job_poll(exz_job *job, int32_t *done, exz_result *result);
+exz_status exz_job_release(exz_job *job);
+size_t exz_job_bytes(const exz_params *params);
+
+/* Human-readable text of a status; last error message of a context. */
+const char *exz_status_string(int status);
+const char *exz_last_error(const exz_ctx *ctx);
+
+/* Diagnostics used by the tests (not needed for correction):
+ * the band bounds L_i, U_i exactly as the device computes them
+ * (TwoSum-based directed rounding), for n values of f (device pointers). */
+exz_status exz_debug_bounds(exz_ctx *ctx, int32_t dtype, const void *f, int64_t n, double xi,
+                            void *L_out, void *U_out, void *stream);
+
+/* Diagnostics: one CheckConstraints pass of g against f, no edit.  Writes
+ * mark_out[i] = 1 for every vertex the rules would decrease (device, n
+ * bytes) and returns |S| in *count. */
+exz_status exz_debug_targets(exz_ctx *ctx, const void *f, const void *g, const exz_params *params,
+                             uint8_t *mark_out, int64_t *count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXACTZ_H */

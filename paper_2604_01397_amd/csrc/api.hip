@@ -1,0 +1,503 @@
+// Host side of the C ABI declared in include/exactz.h: contexts, workspace,
+// the single-field correction driver and the diagnostics entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/exactz.h"
+#include "exz_internal.h"
+#include "exz_host.h"
+
+using namespace exz;
+
+// ---------------------------------------------------------------------------
+// helpers
+
+namespace exz {
+
+void Arena::release() {
+  if (base) (void)hipFree(base);
+  base = nullptr;
+  cap = off = 0;
+}
+
+hipError_t Arena::reserve(size_t bytes) {
+  off = 0;
+  if (bytes <= cap) return hipSuccess;
+  release();
+  const size_t want = bytes + bytes / 8 + 4096;
+  hipError_t e = hipMalloc(&base, want);
+  if (e != hipSuccess) {
+    base = nullptr;
+    (void)hipGetLastError();
+    return e;
+  }
+  cap = want;
+  return hipSuccess;
+}
+
+void *Arena::take(size_t bytes) {
+  off = (off + 255) & ~(size_t)255;
+  void *p = base + off;
+  off += bytes;
+  return p;
+}
+
+size_t Layout::add(size_t bytes) {
+  total = (total + 255) & ~(size_t)255;
+  const size_t at = total;
+  total += bytes;
+  return at;
+}
+
+}  // namespace exz
+
+static exz_status fail(exz_ctx *ctx, exz_status st, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return st;
+}
+
+#define HIP_OR_FAIL(call)                                                               \
+  do {                                                                                  \
+    hipError_t _e = (call);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(ctx, EXZ_E_HIP, "%s failed: %s", #call, hipGetErrorString(_e));        \
+  } while (0)
+
+namespace {
+
+struct Busy {
+  exz_ctx *c;
+  bool ok;
+  explicit Busy(exz_ctx *ctx) : c(ctx), ok(!ctx->busy) {
+    if (ok) c->busy = true;
+  }
+  ~Busy() {
+    if (ok) c->busy = false;
+  }
+};
+
+}  // namespace
+
+namespace exz {
+
+// Validates params and fills geometry, bounds and step of fd.
+exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd) {
+  std::memset(&fd, 0, sizeof fd);
+  if (!p) return fail(ctx, EXZ_E_INVALID, "params is null");
+  if (p->ndim < 1 || p->ndim > 3) return fail(ctx, EXZ_E_INVALID, "ndim must be 1..3");
+  if (p->dtype != EXZ_F32 && p->dtype != EXZ_F64) return fail(ctx, EXZ_E_INVALID, "bad dtype");
+  int64_t d[3] = {1, 1, 1};
+  for (int k = 0; k < p->ndim; ++k) d[k] = p->dims[k];
+  for (int k = p->ndim; k < 3; ++k)
+    if (p->dims[k] != 1 && p->dims[k] != 0)
+      return fail(ctx, EXZ_E_INVALID, "unused dims must be 1");
+  for (int k = 0; k < 3; ++k)
+    if (d[k] < 1) return fail(ctx, EXZ_E_INVALID, "dims must be >= 1");
+  const int64_t n = d[0] * d[1] * d[2];
+  if (d[0] >= (1ll << 31) || d[1] >= (1ll << 31) || d[2] >= (1ll << 31) || n >= (1ll << 31))
+    return fail(ctx, EXZ_E_INVALID, "field has 2^31 or more vertices");
+  if (!(std::isfinite(p->xi) && p->xi > 0)) return fail(ctx, EXZ_E_INVALID, "xi must be finite and > 0");
+  if (p->n_steps < 1 || p->n_steps > 14) return fail(ctx, EXZ_E_INVALID, "n_steps must be 1..14");
+  if (p->event_mode != EXZ_EVENT_REFORMULATED && p->event_mode != EXZ_EVENT_ORIGINAL)
+    return fail(ctx, EXZ_E_INVALID, "bad event_mode");
+  if (p->max_iters < 0) return fail(ctx, EXZ_E_INVALID, "max_iters must be >= 0");
+  fd.nx = (int32_t)d[0];
+  fd.ny = (int32_t)d[1];
+  fd.nz = (int32_t)d[2];
+  fd.n = (int32_t)n;
+  fd.nchunk = (int32_t)((n + 63) / 64);
+  fd.dtype = p->dtype;
+  fd.N = p->n_steps;
+  fd.mode = p->event_mode;
+  fd.resume = p->resume ? 1 : 0;
+  const int ty = ctx ? ctx->tile_y : 4;
+  fd.tile_y = ty;
+  fd.tiles_x = (fd.nx + 63) / 64;
+  fd.tiles_y = (fd.ny + ty - 1) / ty;
+  fd.tile_z = ctx ? ctx->tile_z : 32;
+  fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
+  const int64_t ntiles = (int64_t)fd.tiles_x * fd.tiles_y * fd.tiles_z;
+  if (ntiles >= (1ll << 31)) return fail(ctx, EXZ_E_INVALID, "too many tiles");
+  fd.ntiles = (int32_t)ntiles;
+  const int nxy = fd.nx * fd.ny;
+  for (int s = 0; s < NSLOT; ++s) fd.dlt[s] = DXS[s] + fd.nx * DYS[s] + nxy * DZS[s];
+  fd.dlt[SELF] = 0;
+  // xi_T: largest value of the field type not above xi; Delta = RN(xi_T / N)
+  if (p->dtype == EXZ_F32) {
+    float x = (float)p->xi;
+    if ((double)x > p->xi) x = std::nextafter(x, -INFINITY);
+    if (!(x > 0.0f)) return fail(ctx, EXZ_E_INVALID, "xi rounds to 0 in float32");
+    const volatile float nn = (float)p->n_steps;
+    const volatile float dl = x / nn;
+    fd.xiT = x;
+    fd.delta = dl;
+  } else {
+    const volatile double nn = (double)p->n_steps;
+    const volatile double dl = p->xi / nn;
+    fd.xiT = p->xi;
+    fd.delta = dl;
+  }
+  return EXZ_OK;
+}
+
+// Per-vertex workspace (phase A).
+void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, Layout &L,
+              size_t off[8]) {
+  const size_t n = (size_t)fd.n;
+  off[0] = L.add(sizeof(State));
+  off[1] = L.add(3 * n);                                     // code, low
+  off[2] = L.add(8 * (size_t)fd.nchunk);                     // cpbits
+  off[3] = L.add(4 * ((size_t)fd.nchunk + 1));               // cpoff
+  off[4] = L.add(2 * n);                                     // req
+  off[5] = 0;
+  off[6] = own_cnt ? L.add(n) : 0;                           // cnt
+  off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
+  (void)trace_cap;
+  (void)need_lab;
+}
+
+// Per-critical-point workspace (phase B) for K critical points.
+void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]) {
+  const size_t b = fd.dtype == 0 ? 4 : 8;
+  const size_t kb = b;  // sort key bytes
+  const uint32_t Kc = K ? K : 1;
+  off[0] = 0;
+  off[1] = L.add(4 * (size_t)Kc);  // cp_vtx
+  off[2] = L.add(4 * (size_t)Kc);  // vo2rank
+  off[3] = L.add(4 * (size_t)Kc);  // cp_idx
+  off[4] = L.add(b * Kc);          // cp_val
+  off[5] = L.add(kb * Kc);         // keys
+  off[6] = L.add(kb * Kc);         // keys tmp
+  off[7] = L.add(4 * (size_t)Kc);  // vals
+  off[8] = L.add(4 * (size_t)Kc);  // vals tmp
+  const size_t hw = radix_hist_words(Kc);
+  off[9] = L.add(4 * hw);          // histograms
+  off[10] = L.add(4 * scan_tmp_words((uint32_t)(hw - 1)));
+  off[11] = 0;
+}
+
+// Validation, reference topology, CP order (phases A and B).  On success fd
+// is ready for iterations and ctx->h_state holds the setup flags.
+exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_hat, void *g_out,
+                       uint8_t *cnt_io, int64_t max_iters, Arena &A, Arena &B, hipStream_t s) {
+  fd.f = f;
+  fd.g_hat = g_hat;
+  fd.g = g_out;
+  Layout LA;
+  size_t oa[8];
+  layout_a(fd, cnt_io == nullptr, 0, false, LA, oa);
+  HIP_OR_FAIL(A.reserve(LA.total));
+  char *base = (char *)A.take(LA.total);
+  fd.st = (State *)(base + oa[0]);
+  fd.low = (uint16_t *)(base + oa[1]);
+  fd.code = (uint8_t *)(base + oa[1] + 2 * (size_t)fd.n);
+  fd.cpbits = (unsigned long long *)(base + oa[2]);
+  fd.cpoff = (uint32_t *)(base + oa[3]);
+  fd.req = (uint16_t *)(base + oa[4]);
+  fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
+  uint32_t *scan_tmp = (uint32_t *)(base + oa[7]);
+
+  HIP_OR_FAIL(launch_state_reset(fd, max_iters, s));
+  HIP_OR_FAIL(launch_setup(fd, ctx->d_comp, s));
+  HIP_OR_FAIL(launch_scan_u32(fd.cpoff, fd.cpoff, (uint32_t)fd.nchunk, scan_tmp,
+                              scan_tmp_words((uint32_t)fd.nchunk), s));
+  HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipMemcpyAsync(ctx->h_k, fd.cpoff + fd.nchunk, sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  if (ctx->h_state->err & ERR_NONFINITE) return fail(ctx, EXZ_E_NONFINITE, "NaN or Inf in f or g_hat");
+  if (ctx->h_state->err & ERR_BOUND) return fail(ctx, EXZ_E_BOUND, "g_hat outside [f - xi, f + xi]");
+  const uint32_t K = *ctx->h_k;
+  fd.K = (int32_t)K;
+
+  Layout LB;
+  size_t ob[12];
+  layout_b(fd, K, LB, ob);
+  HIP_OR_FAIL(B.reserve(LB.total));
+  char *bb = (char *)B.take(LB.total);
+  fd.cp_vtx = (uint32_t *)(bb + ob[1]);
+  fd.vo2rank = (uint32_t *)(bb + ob[2]);
+  fd.cp_idx = (uint32_t *)(bb + ob[3]);
+  fd.cp_val = bb + ob[4];
+  void *keys = bb + ob[5];
+  void *keys_tmp = bb + ob[6];
+  uint32_t *vals = (uint32_t *)(bb + ob[7]);
+  uint32_t *vals_tmp = (uint32_t *)(bb + ob[8]);
+  uint32_t *hist = (uint32_t *)(bb + ob[9]);
+  uint32_t *stmp = (uint32_t *)(bb + ob[10]);
+  const size_t hw = radix_hist_words(K ? K : 1);
+  if (K > 0) {
+    HIP_OR_FAIL(launch_cp_compact(fd, ctx->d_comp, keys, s));
+    HIP_OR_FAIL(launch_iota(vals, K, s));
+    HIP_OR_FAIL(launch_radix_sort(fd.dtype == 0 ? 4 : 8, keys, vals, keys_tmp, vals_tmp, K, hist,
+                                  stmp, scan_tmp_words((uint32_t)(hw - 1)), s));
+    HIP_OR_FAIL(launch_cp_init(fd, vals, ctx->d_comp, s));
+  }
+  return EXZ_OK;
+}
+
+}  // namespace exz
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char *exz_status_string(int status) {
+  switch (status) {
+    case EXZ_OK: return "ok";
+    case EXZ_W_STUCK: return "stuck at a fixpoint with residual violations";
+    case EXZ_W_MAX_ITERS: return "stopped at max_iters";
+    case EXZ_E_INVALID: return "invalid argument";
+    case EXZ_E_NONFINITE: return "non-finite input";
+    case EXZ_E_BOUND: return "decompressed field outside the error band";
+    case EXZ_E_NOMEM: return "out of memory";
+    case EXZ_E_HIP: return "HIP runtime error";
+    case EXZ_E_BUSY: return "context busy";
+    default: return "unknown status";
+  }
+}
+
+const char *exz_last_error(const exz_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+exz_status exz_ctx_create(int device, exz_ctx **out) {
+  if (!out) return EXZ_E_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return EXZ_E_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return EXZ_E_HIP;
+  exz_ctx *ctx = new exz_ctx();
+  ctx->device = device;
+  std::vector<uint8_t> comp(1u << NSLOT);
+  build_component_table(comp.data());
+  std::vector<uint32_t> conn(512);
+  build_connected_bits(comp.data(), conn.data());
+  if (hipMalloc(&ctx->d_comp, comp.size()) != hipSuccess ||
+      hipMemcpy(ctx->d_comp, comp.data(), comp.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMalloc(&ctx->d_conn, 512 * sizeof(uint32_t)) != hipSuccess ||
+      hipMemcpy(ctx->d_conn, conn.data(), 512 * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipHostMalloc((void **)&ctx->h_state, sizeof(State) * 2, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&ctx->h_k, 64, hipHostMallocDefault) != hipSuccess) {
+    exz_ctx_destroy(ctx);
+    return EXZ_E_NOMEM;
+  }
+  *out = ctx;
+  return EXZ_OK;
+}
+
+exz_status exz_ctx_destroy(exz_ctx *ctx) {
+  if (!ctx) return EXZ_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->A.release();
+  ctx->B.release();
+  ctx->C.release();
+  for (auto &e : ctx->events) (void)hipEventDestroy(e);
+  if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
+  if (ctx->ev_setup) (void)hipEventDestroy(ctx->ev_setup);
+  if (ctx->ev_end) (void)hipEventDestroy(ctx->ev_end);
+  if (ctx->d_comp) (void)hipFree(ctx->d_comp);
+  if (ctx->d_conn) (void)hipFree(ctx->d_conn);
+  if (ctx->h_state) (void)hipHostFree(ctx->h_state);
+  if (ctx->h_k) (void)hipHostFree(ctx->h_k);
+  delete ctx;
+  return EXZ_OK;
+}
+
+exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value) {
+  if (!ctx || !key) return EXZ_E_INVALID;
+  const std::string k(key);
+  if (k == "profile") {
+    ctx->profile = value != 0;
+  } else if (k == "poll") {
+    if (value < 0 || value > 256) return fail(ctx, EXZ_E_INVALID, "poll must be 0..256");
+    ctx->poll = (int)value;
+  } else if (k == "graph") {
+    ctx->graph = value != 0;
+  } else if (k == "tile_z") {
+    if (value < 1 || value > 1024) return fail(ctx, EXZ_E_INVALID, "tile_z must be 1..1024");
+    ctx->tile_z = (int)value;
+  } else if (k == "tile_y") {
+    if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+      return fail(ctx, EXZ_E_INVALID, "tile_y must be 1, 2, 4, 8 or 16");
+    ctx->tile_y = (int)value;
+  } else {
+    return fail(ctx, EXZ_E_INVALID, "unknown option '%s'", key);
+  }
+  return EXZ_OK;
+}
+
+size_t exz_workspace_bytes(const exz_params *p) {
+  FieldDev fd;
+  if (prepare_field(nullptr, p, fd) != EXZ_OK) return 0;
+  Layout LA, LB;
+  size_t oa[8], ob[12];
+  layout_a(fd, true, 0, p->event_mode == EXZ_EVENT_ORIGINAL || p->certify, LA, oa);
+  layout_b(fd, (uint32_t)fd.n, LB, ob);
+  size_t extra = 0;
+  if (p->event_mode == EXZ_EVENT_ORIGINAL || p->certify) extra = 8 * (size_t)fd.n + 4096;
+  return LA.total + LB.total + extra;
+}
+
+static void fill_result(exz_result *r, const State &st, int status) {
+  r->iterations = st.iterations;
+  r->edited_vertices = st.edited_total;
+  r->edit_ops = st.edit_ops;
+  r->lossless_vertices = st.lossless_total;
+  r->floor_vertices = st.floor_total;
+  r->residual_violations = st.residual;
+  r->status = status;
+}
+
+exz_status exz_correct(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
+                       uint8_t *cnt_io, const exz_params *params, exz_result *result,
+                       void *stream) {
+  exz_result dummy;
+  exz_result *res = result ? result : &dummy;
+  std::memset(res, 0, sizeof *res);
+  res->certified = -1;
+  if (!ctx) return (exz_status)(res->status = EXZ_E_INVALID);
+  Busy busy(ctx);
+  if (!busy.ok) return (exz_status)(res->status = fail(ctx, EXZ_E_BUSY, "context busy"));
+  ctx->last_error.clear();
+  exz_status st = exz_correct_impl(ctx, f, g_hat, g_out, cnt_io, params, res, (hipStream_t)stream);
+  res->status = st;
+  return st;
+}
+
+exz_status exz_debug_bounds(exz_ctx *ctx, int32_t dtype, const void *f, int64_t n, double xi,
+                            void *L_out, void *U_out, void *stream) {
+  if (!ctx || !f || !L_out || !U_out || n < 0) return EXZ_E_INVALID;
+  exz_params p;
+  std::memset(&p, 0, sizeof p);
+  p.ndim = 1;
+  p.dtype = dtype;
+  p.dims[0] = n > 0 ? n : 1;
+  p.dims[1] = p.dims[2] = 1;
+  p.xi = xi;
+  p.n_steps = 5;
+  FieldDev fd;
+  exz_status st = prepare_field(ctx, &p, fd);
+  if (st != EXZ_OK) return st;
+  HIP_OR_FAIL(hipSetDevice(ctx->device));
+  HIP_OR_FAIL(launch_debug_bounds(dtype, f, n, fd.xiT, L_out, U_out, (hipStream_t)stream));
+  HIP_OR_FAIL(hipStreamSynchronize((hipStream_t)stream));
+  return EXZ_OK;
+}
+
+exz_status exz_debug_targets(exz_ctx *ctx, const void *f, const void *g, const exz_params *params,
+                             uint8_t *mark_out, int64_t *count, void *stream) {
+  if (!ctx || !f || !g || !mark_out || !count) return EXZ_E_INVALID;
+  Busy busy(ctx);
+  if (!busy.ok) return fail(ctx, EXZ_E_BUSY, "context busy");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OR_FAIL(hipSetDevice(ctx->device));
+  FieldDev fd;
+  exz_status st = prepare_field(ctx, params, fd);
+  if (st != EXZ_OK) return st;
+  if (params->event_mode != EXZ_EVENT_REFORMULATED)
+    return fail(ctx, EXZ_E_INVALID, "diagnostic check supports the reformulated mode only");
+  // g plays g_hat and g_out at once (no copy); the band check still applies.
+  st = setup_field(ctx, fd, f, g, const_cast<void *>(g), nullptr, 0, ctx->A, ctx->B, s);
+  if (st != EXZ_OK) return st;
+  HIP_OR_FAIL(launch_debug_check(fd, ctx->d_conn, s));
+  HIP_OR_FAIL(launch_targets_to_bytes(fd, mark_out, s));
+  HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  *count = ctx->h_state->ntargets;
+  return EXZ_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// the single-field driver
+
+namespace exz {
+
+exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
+                            uint8_t *cnt_io, const exz_params *params, exz_result *res,
+                            hipStream_t s) {
+  if (!f || !g_hat || !g_out) return fail(ctx, EXZ_E_INVALID, "null field pointer");
+  FieldDev fd;
+  exz_status st = prepare_field(ctx, params, fd);
+  if (st != EXZ_OK) return st;
+  if (params->resume && !cnt_io) return fail(ctx, EXZ_E_INVALID, "resume needs cnt_io");
+  if (params->event_mode == EXZ_EVENT_ORIGINAL)
+    return fail(ctx, EXZ_E_INVALID, "original event mode is not available in this build");
+  HIP_OR_FAIL(hipSetDevice(ctx->device));
+  if (!ctx->ev_start) {
+    HIP_OR_FAIL(hipEventCreate(&ctx->ev_start));
+    HIP_OR_FAIL(hipEventCreate(&ctx->ev_setup));
+    HIP_OR_FAIL(hipEventCreate(&ctx->ev_end));
+  }
+  HIP_OR_FAIL(hipEventRecord(ctx->ev_start, s));
+  st = setup_field(ctx, fd, f, g_hat, g_out, cnt_io, params->max_iters, ctx->A, ctx->B, s);
+  if (st != EXZ_OK) return st;
+  res->num_critical = fd.K;
+  HIP_OR_FAIL(hipEventRecord(ctx->ev_setup, s));
+
+  const int64_t cap = (int64_t)(fd.N + 1) * fd.n + 2;
+  int chunk = ctx->poll > 0 ? ctx->poll : 4;
+  int64_t issued = 0;
+  size_t ev_used = 0;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (ctx->profile) {
+        while (ctx->events.size() < ev_used + 2) {
+          hipEvent_t e;
+          HIP_OR_FAIL(hipEventCreate(&e));
+          ctx->events.push_back(e);
+        }
+        e0 = ctx->events[ev_used];
+        e1 = ctx->events[ev_used + 1];
+        ev_used += 2;
+      }
+      HIP_OR_FAIL(launch_iteration(fd, ctx->d_conn, s, e0, e1));
+    }
+    issued += chunk;
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    if (ctx->h_state->done != RUNNING) break;
+    if (issued > cap) return fail(ctx, EXZ_E_HIP, "loop did not terminate");
+    if (ctx->poll == 0) chunk = std::min(chunk * 2, 32);
+  }
+  HIP_OR_FAIL(hipEventRecord(ctx->ev_end, s));
+  HIP_OR_FAIL(hipEventSynchronize(ctx->ev_end));
+  const State hs = *ctx->h_state;
+  float ms = 0;
+  HIP_OR_FAIL(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_setup));
+  res->setup_ms = ms;
+  HIP_OR_FAIL(hipEventElapsedTime(&ms, ctx->ev_setup, ctx->ev_end));
+  res->loop_ms = ms;
+  int status = EXZ_OK;
+  if (hs.done == STUCK) status = EXZ_W_STUCK;
+  if (hs.done == MAXITERS) status = EXZ_W_MAX_ITERS;
+  fill_result(res, hs, status);
+  if (ctx->profile) {
+    const int64_t real = hs.iterations + (hs.done == MAXITERS ? 0 : 1);
+    double tot = 0;
+    for (int64_t k = 0; k < real && (size_t)(2 * k + 1) < ev_used; ++k) {
+      HIP_OR_FAIL(hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
+      tot += ms;
+    }
+    res->check_launches = real;
+    res->check_ms = tot;
+  }
+  return (exz_status)status;
+}
+
+}  // namespace exz

@@ -1,0 +1,58 @@
+// Host-side structures of the library: the context, workspace arenas and the
+// drivers shared by the single-field, batched and serving entry points.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/exactz.h"
+#include "exz_internal.h"
+
+namespace exz {
+
+// Growable device buffer carved into 256-byte aligned pieces per call.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  hipError_t reserve(size_t bytes);  // resets the carve offset
+  void *take(size_t bytes);
+  void release();
+};
+
+// Size accounting that mirrors Arena::take.
+struct Layout {
+  size_t total = 0;
+  size_t add(size_t bytes);
+};
+
+exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd);
+exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_hat, void *g_out,
+                       uint8_t *cnt_io, int64_t max_iters, Arena &A, Arena &B, hipStream_t s);
+exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
+                            uint8_t *cnt_io, const exz_params *params, exz_result *res,
+                            hipStream_t s);
+void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, Layout &L,
+              size_t off[8]);
+void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]);
+hipError_t launch_iota(uint32_t *v, uint32_t n, hipStream_t s);
+
+}  // namespace exz
+
+struct exz_ctx {
+  int device = 0;
+  bool busy = false;
+  bool profile = false;
+  bool graph = true;
+  int poll = 0;     // 0 = adaptive
+  int tile_y = 4;
+  int tile_z = 32;
+  std::string last_error;
+  uint8_t *d_comp = nullptr;        // link component table (2^14 bytes)
+  uint32_t *d_conn = nullptr;       // one-component bits (2^14 bits)
+  exz::State *h_state = nullptr;    // pinned
+  uint32_t *h_k = nullptr;          // pinned
+  exz::Arena A, B, C;
+  std::vector<hipEvent_t> events;
+  hipEvent_t ev_start = nullptr, ev_setup = nullptr, ev_end = nullptr;
+};

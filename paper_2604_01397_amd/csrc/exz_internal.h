@@ -1,0 +1,243 @@
+// Internal declarations of the gfx950 EXaCTz library: the per-field device
+// descriptor, the loop state, device helpers shared by the kernels and the
+// host-side launch wrappers.  Not part of the public ABI (include/exactz.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace exz {
+
+// ---------------------------------------------------------------------------
+// Mesh: the Freudenthal triangulation of the grid.  Slot s is the neighbour
+// at offset (DX[s], DY[s], DZ[s]); slot 14 stands for the vertex itself.
+// Slots 0..5 are the in-plane offsets, so a 2D field (nz = 1) and a 1D field
+// (ny = nz = 1) use the same tables with the out-of-domain slots masked off.
+constexpr int NSLOT = 14;
+constexpr int SELF = 14;
+constexpr int DXS[NSLOT] = {+1, -1, 0, 0, +1, -1, 0, 0, +1, -1, 0, 0, +1, -1};
+constexpr int DYS[NSLOT] = {0, 0, +1, -1, +1, -1, 0, 0, 0, 0, +1, -1, +1, -1};
+constexpr int DZS[NSLOT] = {0, 0, 0, 0, 0, 0, +1, -1, +1, -1, +1, -1, +1, -1};
+
+// Reference topology of f, per vertex, in two dense arrays:
+//   code  (1 byte)  ascent slot in the low nibble, descent slot in the high
+//                   nibble (SELF for a maximum / minimum);
+//   low   (2 bytes) lower-link slot mask in bits 0..13, LOW_SADDLE if the
+//                   vertex is a saddle of f.
+// Both are read with coalesced loads by the check pass.
+constexpr uint32_t LOW_SADDLE = 1u << 15;
+constexpr uint32_t LOW_MASK = 0x3FFFu;
+
+enum Done : int32_t { RUNNING = 0, CONVERGED = 1, STUCK = 2, MAXITERS = 3 };
+enum SetupErr : uint32_t { ERR_NONFINITE = 1u, ERR_BOUND = 2u };
+
+// Device-resident loop state of one field.  Per-iteration counters are
+// reset by the finalize step; totals accumulate over the call.
+struct State {
+  int32_t done;
+  uint32_t err;
+  uint32_t ntargets;   // |S| of the current iteration (worklist length)
+  uint32_t changed;    // values changed by the current iteration
+  uint32_t lossless;   // (N+1)-th edits in the current iteration
+  uint32_t floored;    // edits that landed on L in the current iteration
+  uint32_t first;      // edits that took a count from 0 to 1
+  uint32_t cert_bad;   // certificate mismatches
+  uint32_t shard[5][64];  // per-iteration counters of the apply pass, sharded by block
+  int64_t iterations;
+  int64_t edit_ops;
+  int64_t lossless_total;
+  int64_t floor_total;
+  int64_t edited_total;
+  int64_t residual;
+  int64_t max_iters;
+  int64_t pad[2];
+};
+
+// Everything a kernel needs to work on one field.  Passed by value to the
+// single-field kernels and stored in a device array for the batched ones.
+struct FieldDev {
+  int32_t nx, ny, nz, n;
+  int32_t nchunk;       // ceil(n / 64): 64-vertex chunks of the CP bitmask
+  int32_t dtype;        // 0 float32, 1 float64
+  int32_t N;            // n_steps
+  int32_t mode;         // event mode
+  int32_t K;            // number of critical points of f
+  int32_t Ks;           // number of saddles of f
+  int32_t resume;
+  int32_t tiles_x, tiles_y;  // z-marching tiles: 64 x tile_y columns ...
+  int32_t tile_y;
+  int32_t tile_z, tiles_z;   // ... of tile_z planes
+  int32_t ntiles;            // tiles_x * tiles_y * tiles_z
+  int32_t trace_cap;
+  int32_t dlt[16];      // linear index offset of each slot (dlt[SELF] = 0)
+  double xiT, delta;    // in the field type, widened exactly to double
+  const void *f;
+  const void *g_hat;
+  void *g;              // the field being corrected (g_out)
+  uint8_t *cnt;
+  uint8_t *code;
+  uint16_t *low;
+  unsigned long long *cpbits;
+  uint32_t *cpoff;      // nchunk + 1 exclusive prefix counts
+  uint32_t *cp_vtx;     // K, vertex order -> vertex
+  uint32_t *vo2rank;    // K, vertex order -> rank in the sorted CP order
+  uint32_t *cp_idx;     // K, rank -> vertex
+  void *cp_val;         // K, rank -> current g value
+  uint32_t *sad_rank;   // Ks, saddle order -> rank in the CP order
+  uint32_t *sel_f;      // 2*Ks: original-mode selections in f (join, split)
+  uint32_t *lab;        // 2*n pointer-jumping labels (original mode / certificate)
+  uint16_t *req;        // n: decrease requests of each vertex (slot mask, bit SELF = itself)
+  int64_t *trace;       // 2 * trace_cap (|S|, changed) per iteration, nullable
+  State *st;
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+// Simulation of Simplicity: (a, ia) < (b, ib).  Bitwise, not short-circuit,
+// so that the compiler emits straight-line compares instead of branches.
+template <class T>
+__device__ __forceinline__ bool sos_lt(T a, uint32_t ia, T b, uint32_t ib) {
+  return (a < b) | ((a == b) & (ia < ib));
+}
+
+template <class T> struct Bits;
+template <> struct Bits<float> {
+  using U = uint32_t;
+  static __device__ __forceinline__ U to(float v) { return __float_as_uint(v); }
+  static __device__ __forceinline__ float from(U u) { return __uint_as_float(u); }
+  static constexpr U SIGN = 0x80000000u;
+  static constexpr U MAXF = 0x7F7FFFFFu;
+};
+template <> struct Bits<double> {
+  using U = unsigned long long;
+  static __device__ __forceinline__ U to(double v) { return (U)__double_as_longlong(v); }
+  static __device__ __forceinline__ double from(U u) { return __longlong_as_double((long long)u); }
+  static constexpr U SIGN = 0x8000000000000000ull;
+  static constexpr U MAXF = 0x7FEFFFFFFFFFFFFFull;
+};
+
+// Next representable value towards +inf / -inf of a finite x.
+template <class T>
+__device__ __forceinline__ T next_up(T x) {
+  using B = Bits<T>;
+  typename B::U u = B::to(x);
+  if ((u & ~B::SIGN) == 0) return B::from(1);  // +-0 -> smallest subnormal
+  return B::from((u & B::SIGN) ? u - 1 : u + 1);
+}
+template <class T>
+__device__ __forceinline__ T next_down(T x) {
+  using B = Bits<T>;
+  typename B::U u = B::to(x);
+  if ((u & ~B::SIGN) == 0) return B::from(B::SIGN | 1);
+  return B::from((u & B::SIGN) ? u + 1 : u - 1);
+}
+
+// Knuth's TwoSum: s = RN(a + b) and the exact error e = (a + b) - s.
+template <class T>
+__device__ __forceinline__ T two_sum(T a, T b, T &e) {
+  T s = a + b;
+  T bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+  return s;
+}
+
+// Lower bound L = RU(f - xiT): the smallest T not below f - xiT.
+template <class T>
+__device__ __forceinline__ T lower_bound(T f, T xiT) {
+  T e;
+  T s = two_sum(f, -xiT, e);
+  if (isinf(s)) return -Bits<T>::from(Bits<T>::MAXF);
+  return e > T(0) ? next_up(s) : s;
+}
+// Upper bound U = RD(f + xiT): the largest T not above f + xiT.
+template <class T>
+__device__ __forceinline__ T upper_bound(T f, T xiT) {
+  T e;
+  T s = two_sum(f, xiT, e);
+  if (isinf(s)) return Bits<T>::from(Bits<T>::MAXF);
+  return e < T(0) ? next_down(s) : s;
+}
+
+// In-domain neighbour slots of (x, y, z).
+__device__ __forceinline__ uint32_t valid_slots(int x, int y, int z, int nx, int ny, int nz) {
+  const bool xm = x > 0, xp = x < nx - 1, ym = y > 0, yp = y < ny - 1, zm = z > 0,
+             zp = z < nz - 1;
+  uint32_t v = 0;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    bool ok = (DXS[s] < 0 ? xm : DXS[s] > 0 ? xp : true) &&
+              (DYS[s] < 0 ? ym : DYS[s] > 0 ? yp : true) &&
+              (DZS[s] < 0 ? zm : DZS[s] > 0 ? zp : true);
+    v |= (uint32_t)ok << s;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int slot_delta(int s, int nx, int nxy) {
+  return DXS[s] + nx * DYS[s] + nxy * DZS[s];
+}
+
+// Block index -> logical work index such that consecutive logical indices
+// run on the same XCD (blocks are dispatched round-robin over the 8 XCDs,
+// each with its own L2): XCD k gets one contiguous range of the work.
+__device__ __forceinline__ uint32_t xcd_swizzle(uint32_t b, uint32_t nb) {
+  const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u, k = b >> 3;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Index of critical point i in vertex order, from the chunk bitmask and the
+// chunk prefix counts.
+__device__ __forceinline__ uint32_t cp_order(const unsigned long long *cpbits, const uint32_t *cpoff,
+                                             uint32_t i) {
+  const uint32_t c = i >> 6;
+  const unsigned long long below = (1ull << (i & 63)) - 1ull;
+  return cpoff[c] + (uint32_t)__popcll(cpbits[c] & below);
+}
+__device__ __forceinline__ bool is_cp(const unsigned long long *cpbits, uint32_t i) {
+  return (cpbits[i >> 6] >> (i & 63)) & 1ull;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+// Component counts of the link subgraph induced by every 14-bit slot mask
+// (2^14 bytes), built on the host from the offset table.
+void build_component_table(uint8_t *out16k);
+// One bit per slot mask: set when the mask induces exactly one connected
+// component of the link (2^14 bits = 512 words).
+void build_connected_bits(const uint8_t *comp16k, uint32_t *out512);
+
+// Launch wrappers (kernels live in setup.hip / loop.hip / sort.hip).
+hipError_t launch_setup(const FieldDev &fd, const uint8_t *comp, hipStream_t s);
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, uint32_t count, uint32_t *tmp,
+                           size_t tmp_words, hipStream_t s);
+size_t scan_tmp_words(uint32_t count);
+hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *comp, void *keys, hipStream_t s);
+hipError_t launch_radix_sort(int key_bytes, void *keys, uint32_t *vals, void *keys_tmp,
+                             uint32_t *vals_tmp, uint32_t count, uint32_t *hist, uint32_t *scan_tmp,
+                             size_t scan_words, hipStream_t s);
+size_t radix_hist_words(uint32_t count);
+hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, const uint8_t *comp,
+                          hipStream_t s);
+hipError_t launch_state_reset(const FieldDev &fd, int64_t max_iters, hipStream_t s);
+hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, hipStream_t s,
+                            hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_certify(const FieldDev &fd, const uint8_t *comp, hipStream_t s);
+hipError_t launch_debug_bounds(int dtype, const void *f, int64_t n, double xiT, void *L, void *U,
+                               hipStream_t s);
+hipError_t launch_debug_check(const FieldDev &fd, const uint32_t *conn, hipStream_t s);
+hipError_t launch_targets_to_bytes(const FieldDev &fd, uint8_t *out, hipStream_t s);
+
+// Batched launches over a device array of FieldDev (see batch.hip).
+struct BatchDev {
+  const FieldDev *fields;    // device array
+  const int32_t *tile_base;  // nfields + 1 prefix of check tiles
+  const int32_t *cp_base;    // nfields + 1 prefix of CP compare items
+  int32_t nfields;
+  int32_t total_tiles;
+  int32_t total_cp;
+};
+hipError_t launch_batch_iteration(const BatchDev &b, const uint8_t *comp, int grid, hipStream_t s);
+
+}  // namespace exz

@@ -1,0 +1,123 @@
+// Stable LSD radix sort of (key, uint32 payload) pairs, 8-bit digits.
+//
+// Sorts the critical points of f by value; the payload is their index in
+// vertex order, and because the input is in vertex order a stable sort
+// yields the Simulation-of-Simplicity order (equal values ascend by index,
+// Sec. 3.3 footnote) that the reformulated event constraints compare
+// against (Sec. 4.3).
+//
+// One pass = per-block digit histograms (digit-major), an exclusive scan of
+// the histograms, and a stable scatter in which each wave ranks equal digits
+// with eight ballots.
+#include "exz_internal.h"
+
+namespace exz {
+
+constexpr int RS_BLOCK = 256;
+constexpr int RS_WAVES = RS_BLOCK / 64;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
+
+template <class K>
+__global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const K *keys, uint32_t count, int shift,
+                                                      uint32_t *hist, uint32_t nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const uint32_t e = base + r * RS_BLOCK + threadIdx.x;
+    if (e < count) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+template <class K>
+__global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uint32_t *vin, K *kout,
+                                                         uint32_t *vout, uint32_t count, int shift,
+                                                         const uint32_t *offs, uint32_t nblocks) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[RS_WAVES][256];
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  base[threadIdx.x] = offs[threadIdx.x * nblocks + blockIdx.x];
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const uint32_t tile = blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const uint32_t e = tile + r * RS_BLOCK + threadIdx.x;
+    const bool valid = e < count;
+    K key = 0;
+    uint32_t val = 0, d = 0;
+    if (valid) {
+      key = kin[e];
+      val = vin[e];
+      d = (uint32_t)(key >> shift) & 255u;
+    }
+    // lanes of this wave holding the same digit
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const unsigned long long bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) wcnt[k][threadIdx.x] = 0;
+    __syncthreads();
+    if (valid && lane == __ffsll((long long)m) - 1) wcnt[w][d] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + (uint32_t)__popcll(m & below);
+      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) add += wcnt[k][threadIdx.x];
+    base[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+size_t radix_hist_words(uint32_t count) {
+  const uint32_t nblocks = (count + RS_TILE - 1) / RS_TILE;
+  return (size_t)256 * (nblocks ? nblocks : 1) + 1;
+}
+
+template <class K>
+static hipError_t sort_impl(K *keys, uint32_t *vals, K *ktmp, uint32_t *vtmp, uint32_t count,
+                            uint32_t *hist, uint32_t *scan_tmp, size_t scan_words, hipStream_t s) {
+  if (count <= 1) return hipSuccess;
+  const uint32_t nblocks = (count + RS_TILE - 1) / RS_TILE;
+  K *ka = keys, *kb = ktmp;
+  uint32_t *va = vals, *vb = vtmp;
+  for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_BLOCK), 0, s, ka, count, shift, hist,
+                       nblocks);
+    hipError_t e = launch_scan_u32(hist, hist, 256u * nblocks, scan_tmp, scan_words, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rs_scatter<K>, dim3(nblocks), dim3(RS_BLOCK), 0, s, ka, va, kb, vb, count,
+                       shift, hist, nblocks);
+    K *kt = ka; ka = kb; kb = kt;
+    uint32_t *vt = va; va = vb; vb = vt;
+  }
+  // an even number of passes leaves the result in (keys, vals)
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_sort(int key_bytes, void *keys, uint32_t *vals, void *keys_tmp,
+                             uint32_t *vals_tmp, uint32_t count, uint32_t *hist, uint32_t *scan_tmp,
+                             size_t scan_words, hipStream_t s) {
+  if (key_bytes == 4)
+    return sort_impl<uint32_t>((uint32_t *)keys, vals, (uint32_t *)keys_tmp, vals_tmp, count, hist,
+                               scan_tmp, scan_words, s);
+  if (key_bytes == 8)
+    return sort_impl<unsigned long long>((unsigned long long *)keys, vals,
+                                         (unsigned long long *)keys_tmp, vals_tmp, count, hist,
+                                         scan_tmp, scan_words, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace exz

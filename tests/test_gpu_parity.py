@@ -1,0 +1,212 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Integer outputs (edit counts, iteration counts, statuses, target sets) and
+the corrected values themselves must be bit-identical: the method is a
+discrete ordering problem with exact IEEE arithmetic on both sides, so the
+tolerance is zero.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_01397_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = exactz.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint32 if a.dtype == np.float32 else np.uint64)
+
+
+def _compare(ctx, f, g, xi, label, n_steps=5, max_iters=0, cnt=None):
+    print("case:", label, f.shape, f.dtype, "xi=%r" % xi, "N=%d" % n_steps,
+          "max_iters=%d" % max_iters, flush=True)
+    fo, go = _dev(f), _dev(g)
+    c_in = _dev(cnt) if cnt is not None else None
+    g_out, c_out, res = ctx.correct(fo, go, xi, n_steps=n_steps, max_iters=max_iters,
+                                    cnt=c_in, resume=cnt is not None)
+    torch.cuda.synchronize()
+    ro, rc, st, _ = oracle.correct(f, g, xi, n_steps=n_steps, max_iters=max_iters, cnt=cnt)
+    assert res["status"] == st["status"], (res, st)
+    assert np.array_equal(_bits(g_out.cpu().numpy()), _bits(ro)), label
+    assert np.array_equal(c_out.cpu().numpy(), rc), label
+    for k in ("iterations", "edited_vertices", "edit_ops", "lossless_vertices",
+              "floor_vertices", "residual_violations", "num_critical"):
+        assert res[k] == st[k], (k, res[k], st[k])
+    return res, st
+
+
+def _rand_case(rng, shape, dtype, kind):
+    n = int(np.prod(shape))
+    if kind == "plateau":
+        f = rng.integers(0, 7, size=n).astype(dtype)
+        xi = 2.0
+        g = f + rng.integers(-8, 9, size=n).astype(dtype) / dtype(4.0)
+    else:
+        f = rng.standard_normal(n).astype(dtype)
+        xi = float(dtype(0.3))
+        g = (f.astype(np.float64) + rng.uniform(-0.29, 0.29, n)).astype(dtype)
+    shp = tuple(reversed(shape))
+    return f.reshape(shp), g.reshape(shp).astype(dtype), xi
+
+
+def test_bounds_match_oracle(ctx):
+    rng = np.random.default_rng(1)
+    for dtype in (np.float32, np.float64):
+        tiny = np.finfo(dtype).tiny
+        vals = np.concatenate([
+            rng.standard_normal(4000) * 10.0 ** rng.integers(-8, 8, 4000),
+            [0.0, -0.0, tiny, -tiny, tiny / 8, -tiny / 8, 1e-8, 5e-9, 1.0, -1.0,
+             np.finfo(dtype).max / 2, -np.finfo(dtype).max, np.finfo(dtype).max],
+        ]).astype(dtype)
+        for xi in (1e-3, 0.3, 1.0, 1.0 / 3.0, 1e-30, 1e30):
+            print("bounds", dtype.__name__, xi, flush=True)
+            L, U = ctx.debug_bounds(_dev(vals), xi)
+            Lr, Ur, _, _ = oracle.bounds(vals, xi)
+            assert np.array_equal(_bits(L.cpu().numpy()), _bits(Lr))
+            # the upper bound can differ only in the sign of a zero
+            assert np.array_equal(U.cpu().numpy(), Ur)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape", [(1,), (2,), (9,), (130,), (5, 4), (67, 3), (3, 70),
+                                   (4, 4, 3), (3, 3, 3), (65, 3, 2), (2, 9, 17), (1, 1, 5)])
+def test_tiny_fields_bit_exact(ctx, shape, dtype):
+    rng = np.random.default_rng(abs(hash((shape, dtype.__name__))) % 2 ** 32)
+    for trial in range(6):
+        f, g, xi = _rand_case(rng, shape, dtype, "plateau" if trial % 2 == 0 else "real")
+        _compare(ctx, f, g, xi, "tiny %s trial %d" % (shape, trial), n_steps=5 if trial % 3 else 2)
+
+
+def test_worked_examples(ctx, golden):
+    for name in ("cascade_1d.txt", "edit_minimum_1d.txt", "floor_collapse_1d.txt"):
+        gd = golden(name)
+        dt = np.dtype(gd["dtype"][0]).type
+        f = np.array([float(v) for v in gd["f"]], dt)
+        g = np.array([float(v) for v in gd["g_hat"]], dt)
+        res, _ = _compare(ctx, f, g, float(gd["xi"][0]), name, n_steps=int(gd["n_steps"][0]))
+        assert res["iterations"] == int(gd["iterations"][0])
+
+
+def test_gauss2d_256_bit_exact(ctx):
+    c = synth.config0()
+    res, st = _compare(ctx, c.f, c.g_hat, c.xi, c.name)
+    assert res["iterations"] > 5
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7])
+def test_per_iteration_states(ctx, k):
+    c = synth.config0()
+    res, _ = _compare(ctx, c.f, c.g_hat, c.xi, c.name, max_iters=k)
+    assert res["status"] == 2 and res["iterations"] == k
+
+
+def test_iteration0_target_set(ctx):
+    for c in (synth.config0(), synth.case_grf3d(40, seed=9, rel=1e-3)):
+        print("targets:", c.name, flush=True)
+        mark, count = ctx.debug_targets(_dev(c.f), _dev(c.g_hat), c.xi)
+        ref = oracle.targets(c.f, c.g_hat)
+        assert count == int(ref.sum())
+        assert np.array_equal(mark.cpu().numpy(), ref)
+
+
+def test_resume_matches(ctx):
+    c = synth.case_gauss2d(80, seed=4, rel=1e-3)
+    f, g = _dev(c.f), _dev(c.g_hat)
+    full, cfull, rfull = ctx.correct(f, g, c.xi)
+    half, chalf, rhalf = ctx.correct(f, g, c.xi, max_iters=3)
+    rest, crest, rrest = ctx.correct(f, half.clone(), c.xi, cnt=chalf.clone(), resume=True)
+    torch.cuda.synchronize()
+    assert rhalf["status"] == 2
+    assert torch.equal(rest, full) and torch.equal(crest, cfull)
+    assert rhalf["iterations"] + rrest["iterations"] == rfull["iterations"]
+
+
+def test_in_place(ctx):
+    c = synth.case_gauss2d(70, seed=5, rel=1e-3)
+    f, g = _dev(c.f), _dev(c.g_hat)
+    ref, cref, _ = ctx.correct(f, g, c.xi)
+    g2 = g.clone()
+    out, cout, _ = ctx.correct(f, g2, c.xi, g_out=g2)
+    torch.cuda.synchronize()
+    assert out.data_ptr() == g2.data_ptr()
+    assert torch.equal(out, ref) and torch.equal(cout, cref)
+
+
+def test_error_statuses(ctx):
+    from paper_2604_01397_amd import exactz
+    f = np.zeros((8, 9), np.float32)
+    g = f.copy()
+    g[3, 3] = np.nan
+    _, _, r = ctx.correct(_dev(f), _dev(g), 0.1, raise_on_error=False)
+    assert r["status"] == exactz.E_NONFINITE
+    g = f.copy()
+    g[2, 5] = np.float32(0.25)
+    _, _, r = ctx.correct(_dev(f), _dev(g), 0.125, raise_on_error=False)
+    assert r["status"] == exactz.E_BOUND
+    g[2, 5] = np.float32(0.125)
+    _, _, r = ctx.correct(_dev(f), _dev(g), 0.125, raise_on_error=False)
+    assert r["status"] == exactz.OK
+    _, _, r = ctx.correct(_dev(f), _dev(f), -1.0, raise_on_error=False)
+    assert r["status"] == exactz.E_INVALID
+    with pytest.raises(exactz.ExactzError):
+        ctx.correct(_dev(f), _dev(f), 0.1, n_steps=0)
+
+
+@pytest.mark.parametrize("tile_y,tile_z", [(1, 32), (2, 5), (8, 1), (16, 64), (4, 7)])
+def test_tile_shape_invariance(ctx, tile_y, tile_z):
+    c = synth.case_grf3d((37, 45, 70), seed=6, rel=1e-3)
+    f, g = _dev(c.f), _dev(c.g_hat)
+    ref, cref, rref = ctx.correct(f, g, c.xi)
+    ctx.set_option("tile_y", tile_y)
+    ctx.set_option("tile_z", tile_z)
+    try:
+        out, cout, r = ctx.correct(f, g, c.xi)
+    finally:
+        ctx.set_option("tile_y", 4)
+        ctx.set_option("tile_z", 32)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref) and torch.equal(cout, cref)
+    assert r["iterations"] == rref["iterations"]
+
+
+@pytest.mark.parametrize("poll", [1, 3, 64])
+def test_poll_interval_invariance(ctx, poll):
+    c = synth.case_gauss2d(100, seed=7, rel=1e-3)
+    f, g = _dev(c.f), _dev(c.g_hat)
+    ref, cref, rref = ctx.correct(f, g, c.xi)
+    ctx.set_option("poll", poll)
+    try:
+        out, cout, r = ctx.correct(f, g, c.xi)
+    finally:
+        ctx.set_option("poll", 0)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref) and torch.equal(cout, cref) and r == {**r, **{k: rref[k] for k in ("iterations", "edit_ops")}}
+
+
+def test_grf128_bit_exact(ctx):
+    c = synth.config1()
+    res, st = _compare(ctx, c.f, c.g_hat, c.xi, c.name)
+    print("128^3:", res, flush=True)
+
+
+def test_float64_grf_bit_exact(ctx):
+    c = synth.case_grf3d(36, seed=12, rel=1e-4, dtype=np.float64, quantizer="lorenzo")
+    _compare(ctx, c.f, c.g_hat, c.xi, c.name)
