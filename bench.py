@@ -58,7 +58,9 @@ def main():
     ap.add_argument("--edge", type=int, default=512, help="field edge (default 512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--poll", type=int, default=0)
-    ap.add_argument("--tile-y", type=int, default=4)
+    ap.add_argument("--tile", type=int, default=404, help="box shape tile_y*100+tile_z")
+    ap.add_argument("--sweep", action="store_true", help="time every compiled box shape first")
+    ap.add_argument("--grid", type=int, default=-1, help="stencil grid (-1 persistent, 0 per box)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -78,7 +80,19 @@ def main():
     g = torch.from_numpy(case.g_hat).to(dev)
     g_out = torch.empty_like(f)
     cnt = torch.zeros(f.shape, dtype=torch.uint8, device=dev)
-    ctx = exactz.Context(0, profile=1, poll=args.poll, tile_y=args.tile_y)
+    ctx = exactz.Context(0, profile=1, poll=args.poll, tile=args.tile, grid=args.grid)
+    if args.sweep:
+        for grid in (-1, 0):
+            ctx.set_option("grid", grid)
+            for shape in (202, 402, 404, 802, 804, 408, 1602):
+                ctx.set_option("tile", shape)
+                ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt, max_iters=2)
+                _, _, r = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt)
+                log("grid %2d tile %4d: check %.4f ms/launch, loop %.2f ms, setup %.2f ms" % (
+                    grid, shape, r["check_ms"] / max(r["check_launches"], 1), r["loop_ms"],
+                    r["setup_ms"]))
+        ctx.set_option("tile", args.tile)
+        ctx.set_option("grid", args.grid)
     stream = torch.cuda.current_stream()
     res = None
     for w in range(args.warmup):

@@ -126,11 +126,12 @@ exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd) {
   fd.tile_y = ty;
   fd.tiles_x = (fd.nx + 63) / 64;
   fd.tiles_y = (fd.ny + ty - 1) / ty;
-  fd.tile_z = ctx ? ctx->tile_z : 32;
+  fd.tile_z = ctx ? ctx->tile_z : 4;
   fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
   const int64_t ntiles = (int64_t)fd.tiles_x * fd.tiles_y * fd.tiles_z;
   if (ntiles >= (1ll << 31)) return fail(ctx, EXZ_E_INVALID, "too many tiles");
   fd.ntiles = (int32_t)ntiles;
+  fd.grid_blocks = ctx ? ctx->grid_blocks : -1;
   const int nxy = fd.nx * fd.ny;
   for (int s = 0; s < NSLOT; ++s) fd.dlt[s] = DXS[s] + fd.nx * DYS[s] + nxy * DZS[s];
   fd.dlt[SELF] = 0;
@@ -160,8 +161,8 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
   off[1] = L.add(3 * n);                                     // code, low
   off[2] = L.add(8 * (size_t)fd.nchunk);                     // cpbits
   off[3] = L.add(4 * ((size_t)fd.nchunk + 1));               // cpoff
-  off[4] = L.add(2 * n);                                     // req
-  off[5] = 0;
+  off[4] = L.add(2 * n + 4);  // req (+4: 32-bit atomics on the last 16-bit word)
+  off[5] = L.add(4 * n);                                     // rank_of
   off[6] = own_cnt ? L.add(n) : 0;                           // cnt
   off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
   (void)trace_cap;
@@ -175,7 +176,7 @@ void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]) {
   const uint32_t Kc = K ? K : 1;
   off[0] = 0;
   off[1] = L.add(4 * (size_t)Kc);  // cp_vtx
-  off[2] = L.add(4 * (size_t)Kc);  // vo2rank
+  off[2] = 0;
   off[3] = L.add(4 * (size_t)Kc);  // cp_idx
   off[4] = L.add(b * Kc);          // cp_val
   off[5] = L.add(kb * Kc);         // keys
@@ -206,6 +207,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   fd.cpbits = (unsigned long long *)(base + oa[2]);
   fd.cpoff = (uint32_t *)(base + oa[3]);
   fd.req = (uint16_t *)(base + oa[4]);
+  fd.rank_of = (uint32_t *)(base + oa[5]);
   fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
   uint32_t *scan_tmp = (uint32_t *)(base + oa[7]);
 
@@ -228,7 +230,6 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   HIP_OR_FAIL(B.reserve(LB.total));
   char *bb = (char *)B.take(LB.total);
   fd.cp_vtx = (uint32_t *)(bb + ob[1]);
-  fd.vo2rank = (uint32_t *)(bb + ob[2]);
   fd.cp_idx = (uint32_t *)(bb + ob[3]);
   fd.cp_val = bb + ob[4];
   void *keys = bb + ob[5];
@@ -244,6 +245,39 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
     HIP_OR_FAIL(launch_radix_sort(fd.dtype == 0 ? 4 : 8, keys, vals, keys_tmp, vals_tmp, K, hist,
                                   stmp, scan_tmp_words((uint32_t)(hw - 1)), s));
     HIP_OR_FAIL(launch_cp_init(fd, vals, ctx->d_comp, s));
+  }
+  return EXZ_OK;
+}
+
+// Path-tracing workspace: original event mode (g labels, f termini, saddle
+// order, f's selections) and/or the certificate (f termini, g labels).
+void layout_c(const FieldDev &fd, bool original, bool certify, Layout &L, size_t off[6]) {
+  const size_t n = (size_t)fd.n, K = (size_t)(fd.K ? fd.K : 1);
+  off[0] = (original || certify) ? L.add(8 * n) : 0;  // lab_f
+  off[1] = (original || certify) ? L.add(8 * n) : 0;  // lab (g) / certificate labels
+  off[2] = original ? L.add(4 * K) : 0;               // sad_rank
+  off[3] = original ? L.add(8 * K) : 0;               // sel_f
+  off[4] = original ? L.add(4 * (K + 1)) : 0;         // saddle flags / prefix
+  off[5] = original ? L.add(4 * scan_tmp_words((uint32_t)K)) : 0;
+}
+
+exz_status setup_paths(exz_ctx *ctx, FieldDev &fd, bool original, bool certify, Arena &C,
+                       uint32_t **lab_g, hipStream_t s) {
+  if (!original && !certify) return EXZ_OK;
+  Layout LC;
+  size_t oc[6];
+  layout_c(fd, original, certify, LC, oc);
+  HIP_OR_FAIL(C.reserve(LC.total));
+  char *cb = (char *)C.take(LC.total);
+  fd.lab_f = (uint32_t *)(cb + oc[0]);
+  fd.lab = (uint32_t *)(cb + oc[1]);
+  *lab_g = fd.lab;
+  if (original) {
+    fd.sad_rank = (uint32_t *)(cb + oc[2]);
+    fd.sel_f = (uint32_t *)(cb + oc[3]);
+    HIP_OR_FAIL(launch_original_setup(fd, ctx->d_comp, (uint32_t *)(cb + oc[4]),
+                                      (uint32_t *)(cb + oc[5]),
+                                      scan_tmp_words((uint32_t)(fd.K ? fd.K : 1)), s));
   }
   return EXZ_OK;
 }
@@ -304,10 +338,20 @@ exz_status exz_ctx_destroy(exz_ctx *ctx) {
   ctx->A.release();
   ctx->B.release();
   ctx->C.release();
+  ctx->BA.release();
+  ctx->BB.release();
+  if (ctx->step_host) (void)hipHostFree(ctx->step_host);
+  if (ctx->step_dev) (void)hipFree(ctx->step_dev);
+  if (ctx->step_copied) (void)hipEventDestroy(ctx->step_copied);
+  if (ctx->order_in) (void)hipEventDestroy(ctx->order_in);
+  if (ctx->order_out) (void)hipEventDestroy(ctx->order_out);
+  if (ctx->work) (void)hipStreamDestroy(ctx->work);
   for (auto &e : ctx->events) (void)hipEventDestroy(e);
   if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
   if (ctx->ev_setup) (void)hipEventDestroy(ctx->ev_setup);
   if (ctx->ev_end) (void)hipEventDestroy(ctx->ev_end);
+  if (ctx->poll_ev[0]) (void)hipEventDestroy(ctx->poll_ev[0]);
+  if (ctx->poll_ev[1]) (void)hipEventDestroy(ctx->poll_ev[1]);
   if (ctx->d_comp) (void)hipFree(ctx->d_comp);
   if (ctx->d_conn) (void)hipFree(ctx->d_conn);
   if (ctx->h_state) (void)hipHostFree(ctx->h_state);
@@ -327,12 +371,21 @@ exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value) {
   } else if (k == "graph") {
     ctx->graph = value != 0;
   } else if (k == "tile_z") {
-    if (value < 1 || value > 1024) return fail(ctx, EXZ_E_INVALID, "tile_z must be 1..1024");
+    if (!box_supported(ctx->tile_y, (int)value))
+      return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", ctx->tile_y, (int)value);
     ctx->tile_z = (int)value;
   } else if (k == "tile_y") {
-    if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
-      return fail(ctx, EXZ_E_INVALID, "tile_y must be 1, 2, 4, 8 or 16");
+    if (!box_supported((int)value, ctx->tile_z))
+      return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", (int)value, ctx->tile_z);
     ctx->tile_y = (int)value;
+  } else if (k == "grid") {  // stencil work-groups: -1 persistent (default), 0 one per box
+    if (value < -1 || value > (1 << 24)) return fail(ctx, EXZ_E_INVALID, "grid must be -1..2^24");
+    ctx->grid_blocks = (int)value;
+  } else if (k == "tile") {  // tile_y * 100 + tile_z, set together
+    const int ty = (int)(value / 100), tz = (int)(value % 100);
+    if (!box_supported(ty, tz)) return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", ty, tz);
+    ctx->tile_y = ty;
+    ctx->tile_z = tz;
   } else {
     return fail(ctx, EXZ_E_INVALID, "unknown option '%s'", key);
   }
@@ -346,9 +399,11 @@ size_t exz_workspace_bytes(const exz_params *p) {
   size_t oa[8], ob[12];
   layout_a(fd, true, 0, p->event_mode == EXZ_EVENT_ORIGINAL || p->certify, LA, oa);
   layout_b(fd, (uint32_t)fd.n, LB, ob);
-  size_t extra = 0;
-  if (p->event_mode == EXZ_EVENT_ORIGINAL || p->certify) extra = 8 * (size_t)fd.n + 4096;
-  return LA.total + LB.total + extra;
+  Layout LC;
+  size_t oc[6];
+  fd.K = fd.n;
+  layout_c(fd, p->event_mode == EXZ_EVENT_ORIGINAL, p->certify != 0, LC, oc);
+  return LA.total + LB.total + LC.total;
 }
 
 static void fill_result(exz_result *r, const State &st, int status) {
@@ -435,8 +490,6 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   exz_status st = prepare_field(ctx, params, fd);
   if (st != EXZ_OK) return st;
   if (params->resume && !cnt_io) return fail(ctx, EXZ_E_INVALID, "resume needs cnt_io");
-  if (params->event_mode == EXZ_EVENT_ORIGINAL)
-    return fail(ctx, EXZ_E_INVALID, "original event mode is not available in this build");
   HIP_OR_FAIL(hipSetDevice(ctx->device));
   if (!ctx->ev_start) {
     HIP_OR_FAIL(hipEventCreate(&ctx->ev_start));
@@ -447,13 +500,26 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   st = setup_field(ctx, fd, f, g_hat, g_out, cnt_io, params->max_iters, ctx->A, ctx->B, s);
   if (st != EXZ_OK) return st;
   res->num_critical = fd.K;
+  uint32_t *lab_g = nullptr;
+  st = setup_paths(ctx, fd, params->event_mode == EXZ_EVENT_ORIGINAL, params->certify != 0,
+                   ctx->C, &lab_g, s);
+  if (st != EXZ_OK) return st;
   HIP_OR_FAIL(hipEventRecord(ctx->ev_setup, s));
 
+  // Iterations are issued in chunks; each chunk ends with an asynchronous
+  // copy of the device state into one of two pinned slots.  The host keeps
+  // one chunk in flight while it reads the previous chunk's state, so the
+  // GPU never waits for the host; after convergence the kernels return at
+  // once, so the chunk issued past the end costs only its launches.
   const int64_t cap = (int64_t)(fd.N + 1) * fd.n + 2;
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   int64_t issued = 0;
   size_t ev_used = 0;
-  for (;;) {
+  if (!ctx->poll_ev[0]) {
+    HIP_OR_FAIL(hipEventCreateWithFlags(&ctx->poll_ev[0], hipEventDisableTiming));
+    HIP_OR_FAIL(hipEventCreateWithFlags(&ctx->poll_ev[1], hipEventDisableTiming));
+  }
+  auto issue_chunk = [&](int slot) -> exz_status {
     for (int k = 0; k < chunk; ++k) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (ctx->profile) {
@@ -466,18 +532,36 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
         e1 = ctx->events[ev_used + 1];
         ev_used += 2;
       }
-      HIP_OR_FAIL(launch_iteration(fd, ctx->d_conn, s, e0, e1));
+      HIP_OR_FAIL(launch_iteration(fd, ctx->d_conn, ctx->d_comp, s, e0, e1));
     }
     issued += chunk;
-    HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(hipStreamSynchronize(s));
-    if (ctx->h_state->done != RUNNING) break;
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state + slot, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipEventRecord(ctx->poll_ev[slot], s));
+    return EXZ_OK;
+  };
+  int slot = 0;
+  st = issue_chunk(slot);
+  if (st != EXZ_OK) return st;
+  for (;;) {
+    if (ctx->poll == 0) chunk = std::min(chunk * 2, 16);
+    st = issue_chunk(1 - slot);
+    if (st != EXZ_OK) return st;
+    HIP_OR_FAIL(hipEventSynchronize(ctx->poll_ev[slot]));
+    if (ctx->h_state[slot].done != RUNNING) break;
     if (issued > cap) return fail(ctx, EXZ_E_HIP, "loop did not terminate");
-    if (ctx->poll == 0) chunk = std::min(chunk * 2, 32);
+    slot = 1 - slot;
+  }
+  // the chunk still in flight ran past the fixpoint; its copy holds the final state
+  HIP_OR_FAIL(hipEventSynchronize(ctx->poll_ev[1 - slot]));
+  ctx->h_state[0] = ctx->h_state[1 - slot];
+  if (params->certify) {
+    HIP_OR_FAIL(launch_certify(fd, ctx->d_comp, lab_g, s));
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
   }
   HIP_OR_FAIL(hipEventRecord(ctx->ev_end, s));
   HIP_OR_FAIL(hipEventSynchronize(ctx->ev_end));
   const State hs = *ctx->h_state;
+  if (params->certify) res->certified = hs.cert_bad == 0 ? 1 : 0;
   float ms = 0;
   HIP_OR_FAIL(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_setup));
   res->setup_ms = ms;

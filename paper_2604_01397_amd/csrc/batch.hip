@@ -1,39 +1,697 @@
-// Batched and serving entry points (many fields per launch).
+// Batched correction and serving: many fields advance together.
+//
+// Every field keeps its own state (Algorithm 1 run per field: own target
+// set, own critical-point order, own convergence flag and counters); what is
+// shared is the launch.  One iteration over the whole batch is four launches
+// of persistent kernels that walk a device-resident list of work items:
+//   check   (field, box) items of every unconverged field,
+//   cpcmp   (field, critical-point pair) items,
+//   apply   (field, box) items,
+//   finalize one wave per field.
+// Items are laid out field after field with a prefix array, so a block finds
+// its field by binary search; blocks of converged fields never get items
+// because the host rebuilds the lists (a few hundred bytes) between polls.
+// The iterations between two polls are replayed from a captured hipGraph:
+// the kernels read their item counts from device memory, so the lists can
+// change between replays without a new capture.
+#include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "exz_host.h"
+#include "loop_box.h"
+
+namespace exz {
+
+struct ItemList {
+  uint32_t nfields;           // active fields
+  uint32_t total;             // items over all active fields
+  const uint32_t *field;      // [nfields] index into the FieldDev array
+  const uint32_t *base;       // [nfields + 1] item prefix
+};
+
+// Field slot of item `it` (largest k with base[k] <= it).
+__device__ __forceinline__ uint32_t find_field(const uint32_t *base, uint32_t nf, uint32_t it) {
+  uint32_t lo = 0, hi = nf;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (base[mid] <= it) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int TY, int TZ>
+__global__ void __launch_bounds__(64 * TY)
+    k_check_batch(const FieldDev *fields, const uint32_t *lists, const uint32_t *conn) {
+  __shared__ double S[Box<TY, TZ>::NE];  // sized for float64; float32 uses the front
+  const uint32_t nf = lists[0], total = lists[1];
+  const uint32_t *field = lists + 2, *base = lists + 2 + nf;
+  for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const uint32_t k = find_field(base, nf, it);
+    const FieldDev &fd = fields[field[k]];
+    if (!fd.st->done) {
+      const BoxOrigin o = box_of(fd, it - base[k], TY, TZ);
+      StageMap<TY, TZ> m;  // per field: its strides differ
+      stage_map<TY, TZ>(fd, threadIdx.y * 64 + threadIdx.x, m);
+      if (fd.dtype == 0)
+        check_box<float, TY, TZ>(fd, conn, o, (float *)S, m);
+      else
+        check_box<double, TY, TZ>(fd, conn, o, S, m);
+    }
+    __syncthreads();
+  }
+}
+
+template <int TY, int TZ>
+__global__ void __launch_bounds__(64 * TY) k_apply_batch(const FieldDev *fields, const uint32_t *lists) {
+  __shared__ uint16_t Q[Box<TY, TZ>::NE];
+  const uint32_t nf = lists[0], total = lists[1];
+  const uint32_t *field = lists + 2, *base = lists + 2 + nf;
+  for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const uint32_t k = find_field(base, nf, it);
+    const FieldDev &fd = fields[field[k]];
+    if (!fd.st->done) {
+      const BoxOrigin o = box_of(fd, it - base[k], TY, TZ);
+      EditCount ec = {{0, 0, 0, 0, 0}};
+      StageMap<TY, TZ> m;
+      stage_map<TY, TZ>(fd, threadIdx.y * 64 + threadIdx.x, m);
+      if (fd.dtype == 0)
+        apply_box<float, TY, TZ>(fd, o, Q, ec, m);
+      else
+        apply_box<double, TY, TZ>(fd, o, Q, ec, m);
+      flush_counts<TY>(fd.st, ec, it);
+    }
+    __syncthreads();
+  }
+}
+
+// Critical-point pairs: field k owns items [base[k], base[k+1]) = its K - 1
+// consecutive pairs.
+__global__ void __launch_bounds__(256) k_cpcmp_batch(const FieldDev *fields, const uint32_t *lists) {
+  const uint32_t nf = lists[0], total = lists[1];
+  const uint32_t *field = lists + 2, *base = lists + 2 + nf;
+  for (uint32_t it = blockIdx.x * 256 + threadIdx.x; it < total; it += gridDim.x * 256) {
+    const uint32_t k = find_field(base, nf, it);
+    const FieldDev &fd = fields[field[k]];
+    if (fd.st->done) continue;
+    const uint32_t r = it - base[k];
+    if (fd.dtype == 0)
+      cp_pair<float>(fd, r);
+    else
+      cp_pair<double>(fd, r);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_finalize_batch(const FieldDev *fields, const uint32_t *lists) {
+  const uint32_t nf = lists[0];
+  if (blockIdx.x < nf) finalize_field(fields[lists[2 + blockIdx.x]]);
+}
+
+// Gathers per-field setup results: err flags and K.
+__global__ void k_gather_setup(const FieldDev *fields, uint32_t nfields, uint32_t *out) {
+  const uint32_t k = blockIdx.x * 64 + threadIdx.x;
+  if (k >= nfields) return;
+  const FieldDev &fd = fields[k];
+  out[2 * k] = fd.st->err;
+  out[2 * k + 1] = fd.cpoff[fd.nchunk];
+}
+
+}  // namespace exz
+
+// ---------------------------------------------------------------------------
+// host side
+
+using namespace exz;
+
+namespace {
+
+exz_status fail_b(exz_ctx *ctx, exz_status st, const char *msg) {
+  if (ctx) ctx->last_error = msg;
+  return st;
+}
+
+#define HIP_OR_FAIL_B(call)                                                                 \
+  do {                                                                                      \
+    hipError_t _e = (call);                                                                 \
+    if (_e != hipSuccess) {                                                                 \
+      if (ctx) ctx->last_error = std::string(#call " failed: ") + hipGetErrorString(_e);     \
+      return EXZ_E_HIP;                                                                     \
+    }                                                                                       \
+  } while (0)
+
+// Per-field host bookkeeping of a batch.
+struct Member {
+  FieldDev fd;
+  int index;          // position in the caller's array
+  exz_status status;  // setup errors
+  bool active;
+  size_t offA, offB;
+  int64_t max_iters;
+  bool certify;
+};
+
+}  // namespace
+
+namespace exz {
+
+// Launch geometry shared by all members of a batch.
+struct BatchShape {
+  int ty3 = 4, tz3 = 4;  // boxes for 3D fields
+  int ty2 = 16, tz2 = 1; // boxes for 1D/2D fields
+};
+
+// Host-built item lists for one phase, in pinned memory.
+struct Lists {
+  std::vector<uint32_t> v;  // [nf, total, field[nf], base[nf+1]]
+  void build(const std::vector<int> &fields, const std::vector<uint32_t> &items) {
+    const uint32_t nf = (uint32_t)fields.size();
+    v.assign(2 + nf + nf + 1, 0);
+    v[0] = nf;
+    uint32_t acc = 0;
+    for (uint32_t k = 0; k < nf; ++k) {
+      v[2 + k] = (uint32_t)fields[k];
+      v[2 + nf + k] = acc;
+      acc += items[k];
+    }
+    v[2 + nf + nf] = acc;
+    v[1] = acc;
+  }
+};
+
+// Runs the batched loop over `members` (already set up, fd.st valid) until
+// every member is done.  dev_fields holds the FieldDev array on the device.
+exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *dev_fields,
+                          const BatchShape &shape, int max_chunks, hipStream_t s);
+
+}  // namespace exz
+
+// Device list buffers: 4 lists (check3, check2, cp, finalize), capacity per
+// list 2 + 2*nf + 1 words.
+static size_t list_words(size_t nf) { return 2 + 2 * nf + 1; }
+
+namespace exz {
+
+static void box_launch_check(int ty, int tz, const FieldDev *fields, const uint32_t *list,
+                             const uint32_t *conn, int grid, hipStream_t s) {
+#define EXZ_BOX_CHECK_B(a, b)                                                                 \
+  if (ty == a && tz == b)                                                                     \
+    hipLaunchKernelGGL((k_check_batch<a, b>), dim3(grid), dim3(64, a), 0, s, fields, list, conn);
+  EXZ_BOX_SHAPES(EXZ_BOX_CHECK_B)
+#undef EXZ_BOX_CHECK_B
+}
+
+static void box_launch_apply(int ty, int tz, const FieldDev *fields, const uint32_t *list, int grid,
+                             hipStream_t s) {
+#define EXZ_BOX_APPLY_B(a, b)                                                                 \
+  if (ty == a && tz == b)                                                                     \
+    hipLaunchKernelGGL((k_apply_batch<a, b>), dim3(grid), dim3(64, a), 0, s, fields, list);
+  EXZ_BOX_SHAPES(EXZ_BOX_APPLY_B)
+#undef EXZ_BOX_APPLY_B
+}
+
+// Issue `iters` batched iterations.
+static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dlists, size_t lw,
+                             const BatchShape &shape, int iters, int grid_box, int grid_cp,
+                             int grid_fin, hipStream_t s) {
+  uint32_t *l3 = dlists, *l2 = dlists + lw, *lc = dlists + 2 * lw, *lf = dlists + 3 * lw;
+  for (int it = 0; it < iters; ++it) {
+    box_launch_check(shape.ty3, shape.tz3, fields, l3, ctx->d_conn, grid_box, s);
+    box_launch_check(shape.ty2, shape.tz2, fields, l2, ctx->d_conn, grid_box, s);
+    hipLaunchKernelGGL(k_cpcmp_batch, dim3(grid_cp), dim3(256), 0, s, fields, lc);
+    box_launch_apply(shape.ty3, shape.tz3, fields, l3, grid_box, s);
+    box_launch_apply(shape.ty2, shape.tz2, fields, l2, grid_box, s);
+    hipLaunchKernelGGL(k_finalize_batch, dim3(grid_fin), dim3(64), 0, s, fields, lf);
+  }
+}
+
+exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *dev_fields,
+                          const BatchShape &shape, int max_chunks, hipStream_t s) {
+  const size_t nf = members.size();
+  const size_t lw = list_words(nf);
+  // device + pinned list buffers
+  std::vector<uint32_t> host(4 * lw, 0);
+  uint32_t *dlists = nullptr, *hl = nullptr;
+  State *hstates = nullptr;
+  HIP_OR_FAIL_B(hipMalloc(&dlists, 4 * lw * sizeof(uint32_t)));
+  struct Free {
+    uint32_t *&d;
+    uint32_t *&h;
+    State *&st;
+    ~Free() {
+      if (d) (void)hipFree(d);
+      if (h) (void)hipHostFree(h);
+      if (st) (void)hipHostFree(st);
+    }
+  } guard{dlists, hl, hstates};
+  HIP_OR_FAIL_B(hipHostMalloc((void **)&hl, 4 * lw * sizeof(uint32_t), hipHostMallocDefault));
+  HIP_OR_FAIL_B(hipHostMalloc((void **)&hstates, std::max<size_t>(nf, 1) * sizeof(State),
+                              hipHostMallocDefault));
+  // persistent grids: enough blocks to fill the chip, never more than items
+  uint64_t max_boxes = 0, max_cp = 0;
+  for (auto &m : members) {
+    max_boxes += (uint64_t)m.fd.ntiles;
+    max_cp += m.fd.K > 1 ? (uint64_t)(m.fd.K - 1) : 0;
+  }
+  const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_boxes, 256 * 8));
+  const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>((max_cp + 255) / 256, 256 * 8));
+  int chunk = ctx->poll > 0 ? ctx->poll : 4;
+  hipGraphExec_t exec = nullptr;
+  int exec_chunk = 0;
+  int grid_fin = (int)nf;
+  for (int round = 0; round < max_chunks; ++round) {
+    // item lists over the active members
+    std::vector<int> f3, f2, fc, fa;
+    std::vector<uint32_t> i3, i2, ic, ia;
+    for (size_t k = 0; k < nf; ++k) {
+      const Member &m = members[k];
+      if (!m.active) continue;
+      const int idx = (int)k;
+      (m.fd.nz > 1 ? f3 : f2).push_back(idx);
+      (m.fd.nz > 1 ? i3 : i2).push_back((uint32_t)m.fd.ntiles);
+      fc.push_back(idx);
+      ic.push_back(m.fd.K > 1 ? (uint32_t)(m.fd.K - 1) : 0u);
+      fa.push_back(idx);
+      ia.push_back(1);
+    }
+    if (fa.empty()) break;
+    Lists L[4];
+    L[0].build(f3, i3);
+    L[1].build(f2, i2);
+    L[2].build(fc, ic);
+    L[3].build(fa, ia);
+    for (int q = 0; q < 4; ++q) std::memcpy(hl + q * lw, L[q].v.data(), L[q].v.size() * 4);
+    HIP_OR_FAIL_B(hipMemcpyAsync(dlists, hl, 4 * lw * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    if (ctx->graph) {
+      if (!exec || exec_chunk != chunk) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        hipGraph_t graph = nullptr;
+        HIP_OR_FAIL_B(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_cp, grid_fin, s);
+        const hipError_t ce = hipStreamEndCapture(s, &graph);  // always ends the capture
+        HIP_OR_FAIL_B(ce);
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_OR_FAIL_B(e);
+        exec_chunk = chunk;
+      }
+      HIP_OR_FAIL_B(hipGraphLaunch(exec, s));
+    } else {
+      issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_cp, grid_fin, s);
+      HIP_OR_FAIL_B(hipGetLastError());
+    }
+    for (size_t k = 0; k < nf; ++k)
+      HIP_OR_FAIL_B(hipMemcpyAsync(hstates + k, members[k].fd.st, sizeof(State),
+                                   hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL_B(hipStreamSynchronize(s));
+    for (size_t k = 0; k < nf; ++k)
+      if (members[k].active && hstates[k].done != RUNNING) members[k].active = false;
+    if (ctx->poll == 0) chunk = std::min(chunk * 2, 32);
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  for (auto &m : members)
+    if (m.active) return fail_b(ctx, EXZ_E_HIP, "batched loop did not terminate");
+  return EXZ_OK;
+}
+
+}  // namespace exz
+
+namespace exz {
+
+hipError_t ensure_work_stream(exz_ctx *ctx) {
+  if (ctx->work) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&ctx->work, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  e = hipEventCreateWithFlags(&ctx->order_in, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  return hipEventCreateWithFlags(&ctx->order_out, hipEventDisableTiming);
+}
+
+}  // namespace exz
 
 extern "C" {
 
 exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfields,
                              exz_result *results, void *stream) {
-  (void)fields; (void)nfields; (void)results; (void)stream;
-  if (ctx) ctx->last_error = "batched correction is not available in this build";
-  return EXZ_E_INVALID;
+  if (!ctx || nfields < 0 || (nfields > 0 && (!fields || !results))) return EXZ_E_INVALID;
+  if (ctx->busy) return fail_b(ctx, EXZ_E_BUSY, "context busy");
+  ctx->busy = true;
+  struct Unbusy {
+    exz_ctx *c;
+    ~Unbusy() { c->busy = false; }
+  } unbusy{ctx};
+  ctx->last_error.clear();
+  HIP_OR_FAIL_B(hipSetDevice(ctx->device));
+  // The iterations are captured into a graph, which HIP does not allow on the
+  // legacy default stream: run on the context's own stream, ordered after the
+  // caller's stream (the call returns only when the work is done).
+  HIP_OR_FAIL_B(ensure_work_stream(ctx));
+  HIP_OR_FAIL_B(hipEventRecord(ctx->order_in, (hipStream_t)stream));
+  HIP_OR_FAIL_B(hipStreamWaitEvent(ctx->work, ctx->order_in, 0));
+  hipStream_t s = ctx->work;
+  exz_status first_err = EXZ_OK;
+  for (int k = 0; k < nfields; ++k) {
+    std::memset(&results[k], 0, sizeof(exz_result));
+    results[k].certified = -1;
+  }
+  std::vector<Member> mem;
+  std::vector<int> singles;  // fields run through the single-field driver
+  BatchShape shape;
+  shape.ty3 = ctx->tile_y;
+  shape.tz3 = ctx->tile_z;
+  for (int k = 0; k < nfields; ++k) {
+    const exz_field &fl = fields[k];
+    Member m;
+    m.index = k;
+    m.status = prepare_field(ctx, &fl.params, m.fd);
+    if (m.status == EXZ_OK && (!fl.f || !fl.g_hat || !fl.g_out))
+      m.status = fail_b(ctx, EXZ_E_INVALID, "null field pointer");
+    if (m.status == EXZ_OK && fl.params.resume && !fl.cnt_io)
+      m.status = fail_b(ctx, EXZ_E_INVALID, "resume needs cnt_io");
+    if (m.status != EXZ_OK) {
+      results[k].status = m.status;
+      if (first_err == EXZ_OK) first_err = m.status;
+      continue;
+    }
+    if (fl.params.event_mode == EXZ_EVENT_ORIGINAL) {
+      singles.push_back(k);
+      continue;
+    }
+    // box shape of the batch for this field's dimensionality
+    const bool three = m.fd.nz > 1;
+    m.fd.tile_y = three ? shape.ty3 : shape.ty2;
+    m.fd.tile_z = three ? shape.tz3 : shape.tz2;
+    m.fd.tiles_y = (m.fd.ny + m.fd.tile_y - 1) / m.fd.tile_y;
+    m.fd.tiles_z = (m.fd.nz + m.fd.tile_z - 1) / m.fd.tile_z;
+    m.fd.ntiles = m.fd.tiles_x * m.fd.tiles_y * m.fd.tiles_z;
+    m.fd.f = fl.f;
+    m.fd.g_hat = fl.g_hat;
+    m.fd.g = fl.g_out;
+    m.max_iters = fl.params.max_iters;
+    m.certify = fl.params.certify != 0;
+    m.active = true;
+    mem.push_back(m);
+  }
+  const size_t nb = mem.size();
+  if (nb) {
+    hipEvent_t e0, e1, e2;
+    HIP_OR_FAIL_B(hipEventCreate(&e0));
+    HIP_OR_FAIL_B(hipEventCreate(&e1));
+    HIP_OR_FAIL_B(hipEventCreate(&e2));
+    HIP_OR_FAIL_B(hipEventRecord(e0, s));
+    // phase A workspaces and states, one allocation
+    Layout LA;
+    std::vector<size_t[8]> oa(nb);
+    std::vector<size_t> baseA(nb);
+    for (size_t k = 0; k < nb; ++k) {
+      Layout L;
+      layout_a(mem[k].fd, fields[mem[k].index].cnt_io == nullptr, 0, false, L, oa[k]);
+      baseA[k] = LA.add(L.total);
+    }
+    const size_t st_off = LA.add(nb * sizeof(State));
+    const size_t fd_off = LA.add(nb * sizeof(FieldDev));
+    const size_t gather_off = LA.add(nb * 2 * sizeof(uint32_t));
+    HIP_OR_FAIL_B(ctx->BA.reserve(LA.total));
+    char *A = (char *)ctx->BA.take(LA.total);
+    State *states = (State *)(A + st_off);
+    FieldDev *dev_fields = (FieldDev *)(A + fd_off);
+    uint32_t *gather = (uint32_t *)(A + gather_off);
+    for (size_t k = 0; k < nb; ++k) {
+      FieldDev &fd = mem[k].fd;
+      char *b = A + baseA[k];
+      fd.st = states + k;
+      fd.low = (uint16_t *)(b + oa[k][1]);
+      fd.code = (uint8_t *)(b + oa[k][1] + 2 * (size_t)fd.n);
+      fd.cpbits = (unsigned long long *)(b + oa[k][2]);
+      fd.cpoff = (uint32_t *)(b + oa[k][3]);
+      fd.req = (uint16_t *)(b + oa[k][4]);
+      fd.rank_of = (uint32_t *)(b + oa[k][5]);
+      uint8_t *cnt_io = fields[mem[k].index].cnt_io;
+      fd.cnt = cnt_io ? cnt_io : (uint8_t *)(b + oa[k][6]);
+      uint32_t *scan_tmp = (uint32_t *)(b + oa[k][7]);
+      HIP_OR_FAIL_B(launch_state_reset(fd, mem[k].max_iters, s));
+      HIP_OR_FAIL_B(launch_setup(fd, ctx->d_comp, s));
+      HIP_OR_FAIL_B(launch_scan_u32(fd.cpoff, fd.cpoff, (uint32_t)fd.nchunk, scan_tmp,
+                                    scan_tmp_words((uint32_t)fd.nchunk), s));
+    }
+    std::vector<FieldDev> host_fd(nb);
+    for (size_t k = 0; k < nb; ++k) host_fd[k] = mem[k].fd;
+    HIP_OR_FAIL_B(hipMemcpyAsync(dev_fields, host_fd.data(), nb * sizeof(FieldDev),
+                                 hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_gather_setup, dim3((unsigned)((nb + 63) / 64)), dim3(64), 0, s, dev_fields,
+                       (uint32_t)nb, gather);
+    std::vector<uint32_t> hg(2 * nb);
+    HIP_OR_FAIL_B(hipMemcpyAsync(hg.data(), gather, 2 * nb * sizeof(uint32_t),
+                                 hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL_B(hipStreamSynchronize(s));
+    // phase B
+    Layout LB;
+    std::vector<size_t[12]> ob(nb);
+    std::vector<size_t> baseB(nb);
+    for (size_t k = 0; k < nb; ++k) {
+      Member &m = mem[k];
+      const uint32_t err = hg[2 * k];
+      if (err & ERR_NONFINITE) m.status = EXZ_E_NONFINITE;
+      else if (err & ERR_BOUND) m.status = EXZ_E_BOUND;
+      if (m.status != EXZ_OK) {
+        m.active = false;
+        results[m.index].status = m.status;
+        if (first_err == EXZ_OK) {
+          first_err = m.status;
+          ctx->last_error = exz_status_string(m.status);
+        }
+        continue;
+      }
+      m.fd.K = (int32_t)hg[2 * k + 1];
+      Layout L;
+      layout_b(m.fd, (uint32_t)m.fd.K, L, ob[k]);
+      baseB[k] = LB.add(L.total);
+    }
+    HIP_OR_FAIL_B(ctx->BB.reserve(LB.total ? LB.total : 256));
+    char *Bm = (char *)ctx->BB.take(LB.total);
+    for (size_t k = 0; k < nb; ++k) {
+      Member &m = mem[k];
+      if (!m.active) continue;
+      FieldDev &fd = m.fd;
+      char *b = Bm + baseB[k];
+      fd.cp_vtx = (uint32_t *)(b + ob[k][1]);
+      fd.cp_idx = (uint32_t *)(b + ob[k][3]);
+      fd.cp_val = b + ob[k][4];
+      const uint32_t K = (uint32_t)fd.K;
+      if (K > 0) {
+        const size_t hw = radix_hist_words(K);
+        HIP_OR_FAIL_B(launch_cp_compact(fd, ctx->d_comp, b + ob[k][5], s));
+        HIP_OR_FAIL_B(launch_iota((uint32_t *)(b + ob[k][7]), K, s));
+        HIP_OR_FAIL_B(launch_radix_sort(fd.dtype == 0 ? 4 : 8, b + ob[k][5], (uint32_t *)(b + ob[k][7]),
+                                        b + ob[k][6], (uint32_t *)(b + ob[k][8]), K,
+                                        (uint32_t *)(b + ob[k][9]), (uint32_t *)(b + ob[k][10]),
+                                        scan_tmp_words((uint32_t)(hw - 1)), s));
+        HIP_OR_FAIL_B(launch_cp_init(fd, (uint32_t *)(b + ob[k][7]), ctx->d_comp, s));
+      }
+      host_fd[k] = fd;
+    }
+    HIP_OR_FAIL_B(hipMemcpyAsync(dev_fields, host_fd.data(), nb * sizeof(FieldDev),
+                                 hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL_B(hipEventRecord(e1, s));
+    std::vector<Member> run;
+    for (auto &m : mem)
+      if (m.active) run.push_back(m);
+    // run only the live members, but index the device array by batch slot
+    for (auto &m : mem) m.active = m.active;  // (kept for clarity)
+    {
+      std::vector<Member> all = mem;  // slot k == device index k
+      const exz_status ls = run_batch_loop(ctx, all, dev_fields, shape, 1 << 30, s);
+      if (ls != EXZ_OK) return ls;
+    }
+    // certificates, then results
+    for (size_t k = 0; k < nb; ++k) {
+      Member &m = mem[k];
+      if (m.status != EXZ_OK || !m.certify) continue;
+      uint32_t *lab_g = nullptr;
+      FieldDev fd = m.fd;
+      const exz_status cs = setup_paths(ctx, fd, false, true, ctx->C, &lab_g, s);
+      if (cs != EXZ_OK) return cs;
+      HIP_OR_FAIL_B(launch_certify(fd, ctx->d_comp, lab_g, s));
+      HIP_OR_FAIL_B(hipStreamSynchronize(s));
+    }
+    HIP_OR_FAIL_B(hipEventRecord(e2, s));
+    std::vector<State> hs(nb);
+    HIP_OR_FAIL_B(hipMemcpyAsync(hs.data(), states, nb * sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL_B(hipStreamSynchronize(s));
+    float setup_ms = 0, loop_ms = 0;
+    (void)hipEventElapsedTime(&setup_ms, e0, e1);
+    (void)hipEventElapsedTime(&loop_ms, e1, e2);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    for (size_t k = 0; k < nb; ++k) {
+      Member &m = mem[k];
+      if (m.status != EXZ_OK) continue;
+      exz_result &r = results[m.index];
+      const State &st = hs[k];
+      r.iterations = st.iterations;
+      r.edited_vertices = st.edited_total;
+      r.edit_ops = st.edit_ops;
+      r.lossless_vertices = st.lossless_total;
+      r.floor_vertices = st.floor_total;
+      r.residual_violations = st.residual;
+      r.num_critical = m.fd.K;
+      r.status = st.done == STUCK ? EXZ_W_STUCK : st.done == MAXITERS ? EXZ_W_MAX_ITERS : EXZ_OK;
+      if (m.certify) r.certified = st.cert_bad == 0 ? 1 : 0;
+      r.setup_ms = setup_ms;  // batch-wide device times
+      r.loop_ms = loop_ms;
+    }
+  }
+  ctx->busy = false;  // the single-field driver takes the context itself
+  for (int k : singles) {
+    const exz_field &fl = fields[k];
+    const exz_status st = exz_correct(ctx, fl.f, fl.g_hat, fl.g_out, fl.cnt_io, &fl.params,
+                                      &results[k], stream);
+    if (st < 0 && first_err == EXZ_OK) first_err = st;
+  }
+  ctx->busy = true;
+  return first_err;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving primitives: jobs advanced together by exz_step
+
+extern "C" {
+
+size_t exz_job_bytes(const exz_params *params) {
+  if (!params || params->event_mode != EXZ_EVENT_REFORMULATED) return 0;
+  return exz_workspace_bytes(params);
 }
 
 exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, exz_job **out) {
-  (void)field; (void)stream;
-  if (out) *out = nullptr;
-  if (ctx) ctx->last_error = "jobs are not available in this build";
-  return EXZ_E_INVALID;
+  if (!ctx || !field || !out) return EXZ_E_INVALID;
+  *out = nullptr;
+  if (field->params.event_mode != EXZ_EVENT_REFORMULATED)
+    return fail_b(ctx, EXZ_E_INVALID, "jobs run the reformulated event constraints only");
+  if (!field->f || !field->g_hat || !field->g_out)
+    return fail_b(ctx, EXZ_E_INVALID, "null field pointer");
+  if (field->params.resume && !field->cnt_io)
+    return fail_b(ctx, EXZ_E_INVALID, "resume needs cnt_io");
+  HIP_OR_FAIL_B(hipSetDevice(ctx->device));
+  exz_job *job = new exz_job();
+  job->ctx = ctx;
+  job->params = field->params;
+  std::memset(&job->result, 0, sizeof job->result);
+  job->result.certified = -1;
+  exz_status st = prepare_field(ctx, &field->params, job->fd);
+  if (st == EXZ_OK) {
+    FieldDev &fd = job->fd;
+    const bool three = fd.nz > 1;  // same boxes as the batched launches
+    fd.tile_y = three ? 4 : 16;
+    fd.tile_z = three ? 4 : 1;
+    fd.tiles_y = (fd.ny + fd.tile_y - 1) / fd.tile_y;
+    fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
+    fd.ntiles = fd.tiles_x * fd.tiles_y * fd.tiles_z;
+    st = setup_field(ctx, fd, field->f, field->g_hat, field->g_out, field->cnt_io,
+                     field->params.max_iters, job->A, job->B, (hipStream_t)stream);
+  }
+  if (st != EXZ_OK) {
+    job->A.release();
+    job->B.release();
+    delete job;
+    return st;
+  }
+  job->result.num_critical = job->fd.K;
+  job->last = (hipStream_t)stream;
+  *out = job;
+  return EXZ_OK;
 }
 
-exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t iters, void *stream) {
-  (void)ctx; (void)jobs; (void)njobs; (void)iters; (void)stream;
-  return EXZ_E_INVALID;
+exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t iters,
+                    void *stream) {
+  if (!ctx || njobs < 0 || iters < 1 || (njobs > 0 && !jobs)) return EXZ_E_INVALID;
+  if (njobs == 0) return EXZ_OK;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OR_FAIL_B(hipSetDevice(ctx->device));
+  const size_t nf = (size_t)njobs;
+  const size_t lw = list_words(nf);
+  const size_t bytes = nf * sizeof(FieldDev) + 4 * lw * sizeof(uint32_t);
+  // staging of the previous step must have been consumed before reuse
+  if (ctx->step_copied) HIP_OR_FAIL_B(hipEventSynchronize(ctx->step_copied));
+  else HIP_OR_FAIL_B(hipEventCreateWithFlags(&ctx->step_copied, hipEventDisableTiming));
+  if (bytes > ctx->step_cap) {
+    if (ctx->step_host) (void)hipHostFree(ctx->step_host);
+    if (ctx->step_dev) (void)hipFree(ctx->step_dev);
+    ctx->step_host = nullptr;
+    ctx->step_dev = nullptr;
+    ctx->step_cap = 0;
+    HIP_OR_FAIL_B(hipHostMalloc(&ctx->step_host, bytes * 2, hipHostMallocDefault));
+    HIP_OR_FAIL_B(hipMalloc(&ctx->step_dev, bytes * 2));
+    ctx->step_cap = bytes * 2;
+  }
+  FieldDev *hf = (FieldDev *)ctx->step_host;
+  uint32_t *hl = (uint32_t *)(hf + nf);
+  std::vector<int> f3, f2, fc, fa;
+  std::vector<uint32_t> i3, i2, ic, ia;
+  uint64_t boxes = 0, cps = 0;
+  for (size_t k = 0; k < nf; ++k) {
+    if (!jobs[k]) return fail_b(ctx, EXZ_E_INVALID, "null job");
+    hf[k] = jobs[k]->fd;
+    const FieldDev &fd = hf[k];
+    (fd.nz > 1 ? f3 : f2).push_back((int)k);
+    (fd.nz > 1 ? i3 : i2).push_back((uint32_t)fd.ntiles);
+    fc.push_back((int)k);
+    ic.push_back(fd.K > 1 ? (uint32_t)(fd.K - 1) : 0u);
+    fa.push_back((int)k);
+    ia.push_back(1);
+    boxes += (uint64_t)fd.ntiles;
+    cps += fd.K > 1 ? (uint64_t)(fd.K - 1) : 0;
+    jobs[k]->last = s;
+  }
+  Lists L[4];
+  L[0].build(f3, i3);
+  L[1].build(f2, i2);
+  L[2].build(fc, ic);
+  L[3].build(fa, ia);
+  for (int q = 0; q < 4; ++q) std::memcpy(hl + q * lw, L[q].v.data(), L[q].v.size() * 4);
+  FieldDev *df = (FieldDev *)ctx->step_dev;
+  uint32_t *dl = (uint32_t *)(df + nf);
+  HIP_OR_FAIL_B(hipMemcpyAsync(df, hf, bytes, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL_B(hipEventRecord(ctx->step_copied, s));
+  BatchShape shape;  // jobs use the default boxes (3D 4 x 4, 2D 16 x 1)
+  const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(boxes, 256 * 8));
+  const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>((cps + 255) / 256, 256 * 8));
+  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, grid_cp, (int)nf, s);
+  HIP_OR_FAIL_B(hipGetLastError());
+  return EXZ_OK;
 }
 
 exz_status exz_job_poll(exz_job *job, int32_t *done, exz_result *result) {
-  (void)job; (void)done; (void)result;
-  return EXZ_E_INVALID;
+  if (!job || !done) return EXZ_E_INVALID;
+  exz_ctx *ctx = job->ctx;
+  HIP_OR_FAIL_B(hipSetDevice(ctx->device));
+  State hs;
+  HIP_OR_FAIL_B(hipMemcpyAsync(&hs, job->fd.st, sizeof(State), hipMemcpyDeviceToHost, job->last));
+  HIP_OR_FAIL_B(hipStreamSynchronize(job->last));
+  *done = hs.done != RUNNING;
+  exz_result &r = job->result;
+  r.iterations = hs.iterations;
+  r.edited_vertices = hs.edited_total;
+  r.edit_ops = hs.edit_ops;
+  r.lossless_vertices = hs.lossless_total;
+  r.floor_vertices = hs.floor_total;
+  r.residual_violations = hs.residual;
+  r.status = hs.done == STUCK ? EXZ_W_STUCK : hs.done == MAXITERS ? EXZ_W_MAX_ITERS : EXZ_OK;
+  if (result) *result = r;
+  return EXZ_OK;
 }
 
 exz_status exz_job_release(exz_job *job) {
-  (void)job;
-  return EXZ_E_INVALID;
+  if (!job) return EXZ_OK;
+  (void)hipSetDevice(job->ctx->device);
+  if (job->last) (void)hipStreamSynchronize(job->last);
+  job->A.release();
+  job->B.release();
+  delete job;
+  return EXZ_OK;
 }
-
-size_t exz_job_bytes(const exz_params *params) { return exz_workspace_bytes(params); }
 
 }  // extern "C"

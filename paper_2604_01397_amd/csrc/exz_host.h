@@ -36,6 +36,10 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
               size_t off[8]);
 void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]);
 hipError_t launch_iota(uint32_t *v, uint32_t n, hipStream_t s);
+void layout_c(const FieldDev &fd, bool original, bool certify, Layout &L, size_t off[6]);
+exz_status setup_paths(exz_ctx *ctx, FieldDev &fd, bool original, bool certify, Arena &C,
+                       uint32_t **lab_g, hipStream_t s);
+hipError_t ensure_work_stream(exz_ctx *ctx);
 
 }  // namespace exz
 
@@ -46,13 +50,35 @@ struct exz_ctx {
   bool graph = true;
   int poll = 0;     // 0 = adaptive
   int tile_y = 4;
-  int tile_z = 32;
+  int tile_z = 4;
+  int grid_blocks = -1;
   std::string last_error;
   uint8_t *d_comp = nullptr;        // link component table (2^14 bytes)
   uint32_t *d_conn = nullptr;       // one-component bits (2^14 bits)
   exz::State *h_state = nullptr;    // pinned
   uint32_t *h_k = nullptr;          // pinned
   exz::Arena A, B, C;
+  exz::Arena BA, BB;  // batched correction workspaces
+  void *step_host = nullptr;  // exz_step staging: pinned FieldDev array + item lists
+  void *step_dev = nullptr;
+  size_t step_cap = 0;
+  hipEvent_t step_copied = nullptr;
+  hipStream_t work = nullptr;       // internal stream for captured work (default priority)
+  hipEvent_t order_in = nullptr, order_out = nullptr;
   std::vector<hipEvent_t> events;
   hipEvent_t ev_start = nullptr, ev_setup = nullptr, ev_end = nullptr;
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
+};
+
+// A serving job: one field whose correction state stays on the device
+// between exz_step calls.
+struct exz_job {
+  exz_ctx *ctx = nullptr;
+  exz::Arena A, B;        // the job's own workspace
+  exz::FieldDev fd;
+  exz_params params;
+  hipStream_t last = nullptr;   // stream of the last work issued for it
+  exz_result result;
+  bool finished = false;
+  hipEvent_t ev_setup = nullptr;
 };

@@ -29,6 +29,7 @@ constexpr uint32_t LOW_SADDLE = 1u << 15;
 constexpr uint32_t LOW_MASK = 0x3FFFu;
 
 enum Done : int32_t { RUNNING = 0, CONVERGED = 1, STUCK = 2, MAXITERS = 3 };
+constexpr int MAX_JUMP_ROUNDS = 34;  // pointer jumping over < 2^32 labels
 enum SetupErr : uint32_t { ERR_NONFINITE = 1u, ERR_BOUND = 2u };
 
 // Device-resident loop state of one field.  Per-iteration counters are
@@ -43,6 +44,8 @@ struct State {
   uint32_t first;      // edits that took a count from 0 to 1
   uint32_t cert_bad;   // certificate mismatches
   uint32_t shard[5][64];  // per-iteration counters of the apply pass, sharded by block
+  uint32_t nsaddle;       // saddles of f (original mode)
+  uint32_t jump[MAX_JUMP_ROUNDS];  // pointer-jumping round flags
   int64_t iterations;
   int64_t edit_ops;
   int64_t lossless_total;
@@ -64,10 +67,10 @@ struct FieldDev {
   int32_t K;            // number of critical points of f
   int32_t Ks;           // number of saddles of f
   int32_t resume;
-  int32_t tiles_x, tiles_y;  // z-marching tiles: 64 x tile_y columns ...
-  int32_t tile_y;
-  int32_t tile_z, tiles_z;   // ... of tile_z planes
+  int32_t tile_y, tile_z;    // stencil boxes of 64 x tile_y x tile_z vertices
+  int32_t tiles_x, tiles_y, tiles_z;
   int32_t ntiles;            // tiles_x * tiles_y * tiles_z
+  int32_t grid_blocks;       // stencil grid: 0 one block per box, < 0 persistent default, > 0 fixed
   int32_t trace_cap;
   int32_t dlt[16];      // linear index offset of each slot (dlt[SELF] = 0)
   double xiT, delta;    // in the field type, widened exactly to double
@@ -80,12 +83,13 @@ struct FieldDev {
   unsigned long long *cpbits;
   uint32_t *cpoff;      // nchunk + 1 exclusive prefix counts
   uint32_t *cp_vtx;     // K, vertex order -> vertex
-  uint32_t *vo2rank;    // K, vertex order -> rank in the sorted CP order
+  uint32_t *rank_of;    // n: rank of a critical point in the sorted CP order, ~0 otherwise
   uint32_t *cp_idx;     // K, rank -> vertex
   void *cp_val;         // K, rank -> current g value
-  uint32_t *sad_rank;   // Ks, saddle order -> rank in the CP order
-  uint32_t *sel_f;      // 2*Ks: original-mode selections in f (join, split)
-  uint32_t *lab;        // 2*n pointer-jumping labels (original mode / certificate)
+  uint32_t *sad_rank;   // saddle order -> rank in the CP order (K capacity)
+  uint32_t *sel_f;      // 2 per saddle: selections in f (join, split) or ~0
+  uint32_t *lab;        // 2n: g's descent / ascent labels (original mode)
+  uint32_t *lab_f;      // 2n: f's resolved path termini (original mode, certificate)
   uint16_t *req;        // n: decrease requests of each vertex (slot mask, bit SELF = itself)
   int64_t *trace;       // 2 * trace_cap (|S|, changed) per iteration, nullable
   State *st;
@@ -174,6 +178,25 @@ __device__ __forceinline__ uint32_t valid_slots(int x, int y, int z, int nx, int
   return v;
 }
 
+// The same set as valid_slots, from six boundary tests instead of per-slot
+// logic (slot groups with a -1 / +1 component along each axis).
+__device__ __forceinline__ uint32_t slots_in_domain(int x, int y, int z, int nx, int ny, int nz) {
+  constexpr uint32_t XN = (1u << 1) | (1u << 5) | (1u << 9) | (1u << 13);
+  constexpr uint32_t XP = (1u << 0) | (1u << 4) | (1u << 8) | (1u << 12);
+  constexpr uint32_t YN = (1u << 3) | (1u << 5) | (1u << 11) | (1u << 13);
+  constexpr uint32_t YP = (1u << 2) | (1u << 4) | (1u << 10) | (1u << 12);
+  constexpr uint32_t ZN = (1u << 7) | (1u << 9) | (1u << 11) | (1u << 13);
+  constexpr uint32_t ZP = (1u << 6) | (1u << 8) | (1u << 10) | (1u << 12);
+  uint32_t out = 0;
+  out |= x == 0 ? XN : 0u;
+  out |= x == nx - 1 ? XP : 0u;
+  out |= y == 0 ? YN : 0u;
+  out |= y == ny - 1 ? YP : 0u;
+  out |= z == 0 ? ZN : 0u;
+  out |= z == nz - 1 ? ZP : 0u;
+  return 0x3FFFu & ~out;
+}
+
 __device__ __forceinline__ int slot_delta(int s, int nx, int nxy) {
   return DXS[s] + nx * DYS[s] + nxy * DZS[s];
 }
@@ -220,10 +243,15 @@ hipError_t launch_radix_sort(int key_bytes, void *keys, uint32_t *vals, void *ke
 size_t radix_hist_words(uint32_t count);
 hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, const uint8_t *comp,
                           hipStream_t s);
+bool box_supported(int tile_y, int tile_z);
 hipError_t launch_state_reset(const FieldDev &fd, int64_t max_iters, hipStream_t s);
-hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, hipStream_t s,
-                            hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_certify(const FieldDev &fd, const uint8_t *comp, hipStream_t s);
+hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,
+                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_certify(const FieldDev &fd, const uint8_t *comp, uint32_t *lab_g, hipStream_t s);
+hipError_t launch_original_setup(const FieldDev &fd, const uint8_t *comp, uint32_t *tmp,
+                                 uint32_t *scan_tmp, size_t scan_words, hipStream_t s);
+hipError_t launch_original_events(const FieldDev &fd, const uint8_t *comp, hipStream_t s);
+int jump_rounds(uint32_t count);
 hipError_t launch_debug_bounds(int dtype, const void *f, int64_t n, double xiT, void *L, void *U,
                                hipStream_t s);
 hipError_t launch_debug_check(const FieldDev &fd, const uint32_t *conn, hipStream_t s);

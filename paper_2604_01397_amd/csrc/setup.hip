@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd, const uint8_
     }
     fd.code[i] = (uint8_t)(asc | (desc << 4));
     fd.low[i] = (uint16_t)low;
+    fd.rank_of[i] = 0xFFFFFFFFu;
     if (fd.g != fd.g_hat) ((T *)fd.g)[i] = gi;
     if (!fd.resume) fd.cnt[i] = 0;
   }
@@ -287,7 +288,7 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint
   const uint32_t vo = sorted_vo[r];
   const uint32_t v = fd.cp_vtx[vo];
   fd.cp_idx[r] = v;
-  fd.vo2rank[vo] = r;
+  fd.rank_of[v] = r;
   ((T *)fd.cp_val)[r] = ((const T *)fd.g)[v];
 }
 

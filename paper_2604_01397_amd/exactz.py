@@ -203,6 +203,41 @@ class Context:
             raise ExactzError(st, self.last_error())
         return g_out, cnt, r.to_dict()
 
+    def correct_batch(self, items, stream=None, raise_on_error=False):
+        """Correct many fields together.
+
+        ``items``: list of dicts with keys f, g_hat, xi and optional n_steps,
+        mode, max_iters, certify, g_out, cnt, resume.  Returns a list of
+        (g_out, cnt, result dict) in the same order.
+        """
+        import torch
+        n = len(items)
+        arr = (Field * max(n, 1))()
+        outs = []
+        for k, it in enumerate(items):
+            f, g = it["f"], it["g_hat"]
+            _check_tensor(f)
+            _check_tensor(g, f)
+            g_out = it.get("g_out")
+            if g_out is None:
+                g_out = torch.empty_like(f)
+            cnt = it.get("cnt")
+            if cnt is None:
+                cnt = torch.zeros(f.shape, dtype=torch.uint8, device=f.device)
+            arr[k].params = make_params(f, it["xi"], it.get("n_steps", 5),
+                                        it.get("mode", REFORMULATED), it.get("max_iters", 0),
+                                        it.get("certify", False), it.get("resume", False))
+            arr[k].f = f.data_ptr()
+            arr[k].g_hat = g.data_ptr()
+            arr[k].g_out = g_out.data_ptr()
+            arr[k].cnt_io = cnt.data_ptr()
+            outs.append((g_out, cnt))
+        res = (Result * max(n, 1))()
+        st = self.lib.exz_correct_batch(self.h, arr, n, res, _stream_ptr(stream))
+        if st < 0 and raise_on_error:
+            raise ExactzError(st, self.last_error())
+        return [(outs[k][0], outs[k][1], res[k].to_dict()) for k in range(n)]
+
     def debug_bounds(self, f, xi, stream=None):
         import torch
         _check_tensor(f)
