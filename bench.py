@@ -8,10 +8,11 @@ One step = one full exz_correct call (validation, reference topology, sorted
 critical points, loop to the fixpoint) from g_hat into a separate output,
 with f and g_hat already resident in HBM.
 
-Prints one JSON line.  ``roofline`` is for the dominant kernel (the dense
-check pass): algorithmic bytes per launch ((b + 1) bytes per vertex: the
-field value and the reference code byte) over its average launch time,
-measured with HIP events on the library's stream during the timed steps.
+Prints one JSON line.  ``roofline`` is for the dominant kernel (the check
+pass): algorithmic bytes ((b + 1) bytes per vertex checked: the field value
+and the reference code byte; a frontier pass checks only the boxes the last
+apply touched) over the check launches' device time, measured with HIP
+events on the library's stream during the timed steps.
 ``cpu_baseline`` is the CPU oracle, single thread, on a bounded sample of
 the same input (a 128^3 sub-block of the field, corrected to convergence).
 """
@@ -61,6 +62,10 @@ def main():
     ap.add_argument("--tile", type=int, default=404, help="box shape tile_y*100+tile_z")
     ap.add_argument("--sweep", action="store_true", help="time every compiled box shape first")
     ap.add_argument("--grid", type=int, default=-1, help="stencil grid (-1 persistent, 0 per box)")
+    ap.add_argument("--frontier", type=int, default=1, help="1: frontier check passes (default)")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="only run a plain 1 GiB read + 1 GiB write elementwise kernel 3 times "
+                         "(scale for the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -69,6 +74,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibrate:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "torch.neg over float32", "read_bytes": src.numel() * 4,
+                          "write_bytes": dst.numel() * 4, "launches": 3}), flush=True)
+        return
 
     from paper_2604_01397_amd import exactz, synth
 
@@ -80,19 +95,24 @@ def main():
     g = torch.from_numpy(case.g_hat).to(dev)
     g_out = torch.empty_like(f)
     cnt = torch.zeros(f.shape, dtype=torch.uint8, device=dev)
-    ctx = exactz.Context(0, profile=1, poll=args.poll, tile=args.tile, grid=args.grid)
+    ctx = exactz.Context(0, profile=1, poll=args.poll, tile=args.tile, grid=args.grid,
+                         frontier=args.frontier)
     if args.sweep:
-        for grid in (-1, 0):
-            ctx.set_option("grid", grid)
-            for shape in (202, 402, 404, 802, 804, 408, 1602):
-                ctx.set_option("tile", shape)
-                ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt, max_iters=2)
-                _, _, r = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt)
-                log("grid %2d tile %4d: check %.4f ms/launch, loop %.2f ms, setup %.2f ms" % (
-                    grid, shape, r["check_ms"] / max(r["check_launches"], 1), r["loop_ms"],
-                    r["setup_ms"]))
+        for fr in (0, 1):
+            ctx.set_option("frontier", fr)
+            for grid in (-1, 0):
+                ctx.set_option("grid", grid)
+                for shape in (202, 402, 404, 802, 804, 408, 1602):
+                    ctx.set_option("tile", shape)
+                    ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt, max_iters=2)
+                    _, _, r = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt)
+                    log("frontier %d grid %2d tile %4d: check %.4f ms/launch (%d launches, "
+                        "%.3g vertices), loop %.2f ms, setup %.2f ms" % (
+                            fr, grid, shape, r["check_ms"] / max(r["check_launches"], 1),
+                            r["check_launches"], r["check_vertices"], r["loop_ms"], r["setup_ms"]))
         ctx.set_option("tile", args.tile)
         ctx.set_option("grid", args.grid)
+        ctx.set_option("frontier", args.frontier)
     stream = torch.cuda.current_stream()
     res = None
     for w in range(args.warmup):
@@ -100,12 +120,13 @@ def main():
         log("warmup %d: %s" % (w, res))
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    check_ms, check_n = 0.0, 0
+    check_ms, check_n, check_v = 0.0, 0, 0
     results = []
     for k in range(args.steps):
         _, _, res = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt, stream=stream)
         check_ms += res["check_ms"]
         check_n += res["check_launches"]
+        check_v += res["check_vertices"]
         results.append(res)
         log("step %d: iters=%d edited=%d status=%d setup=%.2f ms loop=%.2f ms" % (
             k, res["iterations"], res["edited_vertices"], res["status"], res["setup_ms"],
@@ -117,8 +138,8 @@ def main():
     b = case.f.itemsize
     value = n * b / (ms * 1e-3) / 1e9
     avg_check_ms = check_ms / max(check_n, 1)
-    algo_bytes = (b + 1) * n
-    achieved = algo_bytes / (avg_check_ms * 1e-3) / 1e9
+    algo_bytes = (b + 1) * check_v / max(check_n, 1)  # per launch, on average
+    achieved = (b + 1) * check_v / (check_ms * 1e-3) / 1e9
     line = {
         "metric": "GB/s of field corrected on 1 MI355X (plain)",
         "value": round(value, 3),
@@ -136,11 +157,12 @@ def main():
                                "quantiser, eps = 1e-4 range, N = 5, reformulated" % args.edge,
                    "n": n, "iterations": res["iterations"], "edited_vertices": res["edited_vertices"],
                    "num_critical": res["num_critical"], "setup_ms": round(res["setup_ms"], 3),
-                   "loop_ms": round(res["loop_ms"], 3)},
+                   "loop_ms": round(res["loop_ms"], 3), "frontier": args.frontier},
         "roofline": {"bound": "hbm", "kernel": "k_check", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "avg_launch_ms": round(avg_check_ms, 5),
-                     "launches": check_n, "bytes_per_launch": algo_bytes},
+                     "launches": check_n, "bytes_per_launch": round(algo_bytes),
+                     "vertices_checked_per_step": check_v // args.steps},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sub-block ...")

@@ -98,8 +98,11 @@ typedef struct {
   int32_t certified;           /* -1 not run, 0 mismatch, 1 identical */
   double setup_ms;             /* device time of validation + reference topology */
   double loop_ms;              /* device time of the correction loop */
-  int64_t check_launches;      /* profiling: check passes that did work */
+  int64_t check_launches;      /* profiling: check launches issued (those
+                                  past the fixpoint return at once) */
   double check_ms;             /* profiling: their summed device time */
+  int64_t check_vertices;      /* profiling: vertices they checked (a
+                                  frontier pass checks changed boxes only) */
 } exz_result;
 
 typedef struct exz_ctx exz_ctx;
@@ -112,14 +115,22 @@ exz_status exz_ctx_create(int device, exz_ctx **out);
 /* Release the context and its workspace.  NULL is accepted. */
 exz_status exz_ctx_destroy(exz_ctx *ctx);
 
-/* Tuning and diagnostics.  Keys:
+/* Tuning and diagnostics.  None of them changes a result.  Keys:
  *   "profile"  0/1: record device events around every check pass and
- *              report check_launches / check_ms;
+ *              report check_launches / check_ms / check_vertices;
  *   "poll"     iterations issued between two host polls (1..256; default:
  *              adaptive, starting at 4);
  *   "graph"    0/1: replay the iterations between polls from a captured
- *              hipGraph (default 1);
- *   "tile_y"   rows per check work-group (1, 2, 4, 8, 16; default 4).
+ *              hipGraph (batched calls; default 1);
+ *   "tile"     check box 64 x tile_y x tile_z given as tile_y * 100 + tile_z;
+ *              compiled boxes (y, z): (1,1) (2,2) (4,1) (4,2) (4,4) (8,1)
+ *              (8,2) (8,4) (4,8) (16,1) (16,2); default 404.  "tile_y" and
+ *              "tile_z" set one side;
+ *   "grid"     check work-groups: -1 persistent (default), 0 one per box,
+ *              > 0 that many (persistent);
+ *   "frontier" 0/1: after the first pass, re-check only boxes in which the
+ *              last apply changed a value or count (reformulated mode;
+ *              default 1).
  * Returns EXZ_E_INVALID for an unknown key or value. */
 exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value);
 

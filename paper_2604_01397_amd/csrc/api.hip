@@ -132,6 +132,9 @@ exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd) {
   if (ntiles >= (1ll << 31)) return fail(ctx, EXZ_E_INVALID, "too many tiles");
   fd.ntiles = (int32_t)ntiles;
   fd.grid_blocks = ctx ? ctx->grid_blocks : -1;
+  // original mode rewrites g's pointer labels by pointer jumping every
+  // iteration, so its check pass always covers every box
+  fd.frontier = (ctx ? ctx->frontier : true) && p->event_mode == EXZ_EVENT_REFORMULATED;
   const int nxy = fd.nx * fd.ny;
   for (int s = 0; s < NSLOT; ++s) fd.dlt[s] = DXS[s] + fd.nx * DYS[s] + nxy * DZS[s];
   fd.dlt[SELF] = 0;
@@ -155,16 +158,19 @@ exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd) {
 
 // Per-vertex workspace (phase A).
 void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, Layout &L,
-              size_t off[8]) {
+              size_t off[9]) {
   const size_t n = (size_t)fd.n;
   off[0] = L.add(sizeof(State));
   off[1] = L.add(3 * n);                                     // code, low
   off[2] = L.add(8 * (size_t)fd.nchunk);                     // cpbits
   off[3] = L.add(4 * ((size_t)fd.nchunk + 1));               // cpoff
-  off[4] = L.add(2 * n + 4);  // req (+4: 32-bit atomics on the last 16-bit word)
+  off[4] = L.add(8 * (size_t)fd.nchunk);                     // target bitmask
   off[5] = L.add(4 * n);                                     // rank_of
   off[6] = own_cnt ? L.add(n) : 0;                           // cnt
   off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
+  // dirty box flags, sized for the smallest box (64 x 1 x 1) so the
+  // footprint does not depend on the box shape
+  off[8] = L.add((size_t)fd.tiles_x * (size_t)fd.ny * (size_t)fd.nz);
   (void)trace_cap;
   (void)need_lab;
 }
@@ -197,7 +203,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   fd.g_hat = g_hat;
   fd.g = g_out;
   Layout LA;
-  size_t oa[8];
+  size_t oa[9];
   layout_a(fd, cnt_io == nullptr, 0, false, LA, oa);
   HIP_OR_FAIL(A.reserve(LA.total));
   char *base = (char *)A.take(LA.total);
@@ -206,7 +212,8 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   fd.code = (uint8_t *)(base + oa[1] + 2 * (size_t)fd.n);
   fd.cpbits = (unsigned long long *)(base + oa[2]);
   fd.cpoff = (uint32_t *)(base + oa[3]);
-  fd.req = (uint16_t *)(base + oa[4]);
+  fd.tbits = (uint32_t *)(base + oa[4]);
+  fd.bdirty = (uint8_t *)(base + oa[8]);
   fd.rank_of = (uint32_t *)(base + oa[5]);
   fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
   uint32_t *scan_tmp = (uint32_t *)(base + oa[7]);
@@ -378,6 +385,8 @@ exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value) {
     if (!box_supported((int)value, ctx->tile_z))
       return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", (int)value, ctx->tile_z);
     ctx->tile_y = (int)value;
+  } else if (k == "frontier") {  // 1: re-check only changed boxes (reformulated mode)
+    ctx->frontier = value != 0;
   } else if (k == "grid") {  // stencil work-groups: -1 persistent (default), 0 one per box
     if (value < -1 || value > (1 << 24)) return fail(ctx, EXZ_E_INVALID, "grid must be -1..2^24");
     ctx->grid_blocks = (int)value;
@@ -396,7 +405,7 @@ size_t exz_workspace_bytes(const exz_params *p) {
   FieldDev fd;
   if (prepare_field(nullptr, p, fd) != EXZ_OK) return 0;
   Layout LA, LB;
-  size_t oa[8], ob[12];
+  size_t oa[9], ob[12];
   layout_a(fd, true, 0, p->event_mode == EXZ_EVENT_ORIGINAL || p->certify, LA, oa);
   layout_b(fd, (uint32_t)fd.n, LB, ob);
   Layout LC;
@@ -511,7 +520,7 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   // one chunk in flight while it reads the previous chunk's state, so the
   // GPU never waits for the host; after convergence the kernels return at
   // once, so the chunk issued past the end costs only its launches.
-  const int64_t cap = (int64_t)(fd.N + 1) * fd.n + 2;
+  const int64_t cap = (int64_t)(fd.N + 1) * fd.n + 3;  // + final and confirming passes
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   int64_t issued = 0;
   size_t ev_used = 0;
@@ -572,14 +581,17 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   if (hs.done == MAXITERS) status = EXZ_W_MAX_ITERS;
   fill_result(res, hs, status);
   if (ctx->profile) {
-    const int64_t real = hs.iterations + (hs.done == MAXITERS ? 0 : 1);
+    // every check launch issued, those past the fixpoint included (they
+    // return at once), so the average matches a kernel trace of the call
+    const int64_t launched = (int64_t)(ev_used / 2);
     double tot = 0;
-    for (int64_t k = 0; k < real && (size_t)(2 * k + 1) < ev_used; ++k) {
+    for (int64_t k = 0; k < launched; ++k) {
       HIP_OR_FAIL(hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
       tot += ms;
     }
-    res->check_launches = real;
+    res->check_launches = launched;
     res->check_ms = tot;
+    res->check_vertices = (int64_t)hs.checked;
   }
   return (exz_status)status;
 }

@@ -63,24 +63,25 @@ __global__ void __launch_bounds__(64 * TY)
   }
 }
 
-template <int TY, int TZ>
-__global__ void __launch_bounds__(64 * TY) k_apply_batch(const FieldDev *fields, const uint32_t *lists) {
-  __shared__ uint16_t Q[Box<TY, TZ>::NE];
+// ApplyBoundedEdits: field k owns items [base[k], base[k+1]), one per 256
+// words of its target set.
+__global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *fields,
+                                                             const uint32_t *lists) {
   const uint32_t nf = lists[0], total = lists[1];
   const uint32_t *field = lists + 2, *base = lists + 2 + nf;
   for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
     const uint32_t k = find_field(base, nf, it);
     const FieldDev &fd = fields[field[k]];
     if (!fd.st->done) {
-      const BoxOrigin o = box_of(fd, it - base[k], TY, TZ);
       EditCount ec = {{0, 0, 0, 0, 0}};
-      StageMap<TY, TZ> m;
-      stage_map<TY, TZ>(fd, threadIdx.y * 64 + threadIdx.x, m);
-      if (fd.dtype == 0)
-        apply_box<float, TY, TZ>(fd, o, Q, ec, m);
-      else
-        apply_box<double, TY, TZ>(fd, o, Q, ec, m);
-      flush_counts<TY>(fd.st, ec, it);
+      const uint32_t w = (it - base[k]) * APPLY_BLOCK + threadIdx.x;
+      if (w < (uint32_t)(2 * fd.nchunk)) {
+        if (fd.dtype == 0)
+          apply_word<float>(fd, w, ec);
+        else
+          apply_word<double>(fd, w, ec);
+      }
+      flush_counts<APPLY_BLOCK / 64>(fd.st, ec, it);
     }
     __syncthreads();
   }
@@ -186,8 +187,9 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
 
 }  // namespace exz
 
-// Device list buffers: 4 lists (check3, check2, cp, finalize), capacity per
-// list 2 + 2*nf + 1 words.
+// Device list buffers: NLISTS lists (check3, check2, cp, finalize, apply),
+// capacity per list 2 + 2*nf + 1 words.
+constexpr int NLISTS = 5;
 static size_t list_words(size_t nf) { return 2 + 2 * nf + 1; }
 
 namespace exz {
@@ -201,28 +203,24 @@ static void box_launch_check(int ty, int tz, const FieldDev *fields, const uint3
 #undef EXZ_BOX_CHECK_B
 }
 
-static void box_launch_apply(int ty, int tz, const FieldDev *fields, const uint32_t *list, int grid,
-                             hipStream_t s) {
-#define EXZ_BOX_APPLY_B(a, b)                                                                 \
-  if (ty == a && tz == b)                                                                     \
-    hipLaunchKernelGGL((k_apply_batch<a, b>), dim3(grid), dim3(64, a), 0, s, fields, list);
-  EXZ_BOX_SHAPES(EXZ_BOX_APPLY_B)
-#undef EXZ_BOX_APPLY_B
-}
-
 // Issue `iters` batched iterations.
 static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dlists, size_t lw,
                              const BatchShape &shape, int iters, int grid_box, int grid_cp,
-                             int grid_fin, hipStream_t s) {
-  uint32_t *l3 = dlists, *l2 = dlists + lw, *lc = dlists + 2 * lw, *lf = dlists + 3 * lw;
+                             int grid_fin, int grid_apply, hipStream_t s) {
+  uint32_t *l3 = dlists, *l2 = dlists + lw, *lc = dlists + 2 * lw, *lf = dlists + 3 * lw,
+           *la = dlists + 4 * lw;
   for (int it = 0; it < iters; ++it) {
     box_launch_check(shape.ty3, shape.tz3, fields, l3, ctx->d_conn, grid_box, s);
     box_launch_check(shape.ty2, shape.tz2, fields, l2, ctx->d_conn, grid_box, s);
     hipLaunchKernelGGL(k_cpcmp_batch, dim3(grid_cp), dim3(256), 0, s, fields, lc);
-    box_launch_apply(shape.ty3, shape.tz3, fields, l3, grid_box, s);
-    box_launch_apply(shape.ty2, shape.tz2, fields, l2, grid_box, s);
+    hipLaunchKernelGGL(k_apply_batch, dim3(grid_apply), dim3(APPLY_BLOCK), 0, s, fields, la);
     hipLaunchKernelGGL(k_finalize_batch, dim3(grid_fin), dim3(64), 0, s, fields, lf);
   }
+}
+
+// Items of the apply pass of one field: 256 target words each.
+static uint32_t apply_items(const FieldDev &fd) {
+  return (uint32_t)((2 * fd.nchunk + APPLY_BLOCK - 1) / APPLY_BLOCK);
 }
 
 exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *dev_fields,
@@ -230,10 +228,10 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   const size_t nf = members.size();
   const size_t lw = list_words(nf);
   // device + pinned list buffers
-  std::vector<uint32_t> host(4 * lw, 0);
+  std::vector<uint32_t> host(NLISTS * lw, 0);
   uint32_t *dlists = nullptr, *hl = nullptr;
   State *hstates = nullptr;
-  HIP_OR_FAIL_B(hipMalloc(&dlists, 4 * lw * sizeof(uint32_t)));
+  HIP_OR_FAIL_B(hipMalloc(&dlists, NLISTS * lw * sizeof(uint32_t)));
   struct Free {
     uint32_t *&d;
     uint32_t *&h;
@@ -244,16 +242,18 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
       if (st) (void)hipHostFree(st);
     }
   } guard{dlists, hl, hstates};
-  HIP_OR_FAIL_B(hipHostMalloc((void **)&hl, 4 * lw * sizeof(uint32_t), hipHostMallocDefault));
+  HIP_OR_FAIL_B(hipHostMalloc((void **)&hl, NLISTS * lw * sizeof(uint32_t), hipHostMallocDefault));
   HIP_OR_FAIL_B(hipHostMalloc((void **)&hstates, std::max<size_t>(nf, 1) * sizeof(State),
                               hipHostMallocDefault));
   // persistent grids: enough blocks to fill the chip, never more than items
-  uint64_t max_boxes = 0, max_cp = 0;
+  uint64_t max_boxes = 0, max_cp = 0, max_apply = 0;
   for (auto &m : members) {
     max_boxes += (uint64_t)m.fd.ntiles;
     max_cp += m.fd.K > 1 ? (uint64_t)(m.fd.K - 1) : 0;
+    max_apply += apply_items(m.fd);
   }
   const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_boxes, 256 * 8));
+  const int grid_apply = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_apply, 256 * 16));
   const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>((max_cp + 255) / 256, 256 * 8));
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   hipGraphExec_t exec = nullptr;
@@ -262,7 +262,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   for (int round = 0; round < max_chunks; ++round) {
     // item lists over the active members
     std::vector<int> f3, f2, fc, fa;
-    std::vector<uint32_t> i3, i2, ic, ia;
+    std::vector<uint32_t> i3, i2, ic, ia, iw;
     for (size_t k = 0; k < nf; ++k) {
       const Member &m = members[k];
       if (!m.active) continue;
@@ -273,22 +273,26 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
       ic.push_back(m.fd.K > 1 ? (uint32_t)(m.fd.K - 1) : 0u);
       fa.push_back(idx);
       ia.push_back(1);
+      iw.push_back(apply_items(m.fd));
     }
     if (fa.empty()) break;
-    Lists L[4];
+    Lists L[NLISTS];
     L[0].build(f3, i3);
     L[1].build(f2, i2);
     L[2].build(fc, ic);
     L[3].build(fa, ia);
-    for (int q = 0; q < 4; ++q) std::memcpy(hl + q * lw, L[q].v.data(), L[q].v.size() * 4);
-    HIP_OR_FAIL_B(hipMemcpyAsync(dlists, hl, 4 * lw * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    L[4].build(fa, iw);
+    for (int q = 0; q < NLISTS; ++q) std::memcpy(hl + q * lw, L[q].v.data(), L[q].v.size() * 4);
+    HIP_OR_FAIL_B(hipMemcpyAsync(dlists, hl, NLISTS * lw * sizeof(uint32_t),
+                                 hipMemcpyHostToDevice, s));
     if (ctx->graph) {
       if (!exec || exec_chunk != chunk) {
         if (exec) (void)hipGraphExecDestroy(exec);
         exec = nullptr;
         hipGraph_t graph = nullptr;
         HIP_OR_FAIL_B(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_cp, grid_fin, s);
+        issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_cp, grid_fin,
+                         grid_apply, s);
         const hipError_t ce = hipStreamEndCapture(s, &graph);  // always ends the capture
         HIP_OR_FAIL_B(ce);
         const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -298,7 +302,8 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
       }
       HIP_OR_FAIL_B(hipGraphLaunch(exec, s));
     } else {
-      issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_cp, grid_fin, s);
+      issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_cp, grid_fin,
+                         grid_apply, s);
       HIP_OR_FAIL_B(hipGetLastError());
     }
     for (size_t k = 0; k < nf; ++k)
@@ -385,6 +390,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     m.fd.tiles_y = (m.fd.ny + m.fd.tile_y - 1) / m.fd.tile_y;
     m.fd.tiles_z = (m.fd.nz + m.fd.tile_z - 1) / m.fd.tile_z;
     m.fd.ntiles = m.fd.tiles_x * m.fd.tiles_y * m.fd.tiles_z;
+    m.fd.frontier = 0;  // batched check passes cover every box
     m.fd.f = fl.f;
     m.fd.g_hat = fl.g_hat;
     m.fd.g = fl.g_out;
@@ -402,7 +408,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     HIP_OR_FAIL_B(hipEventRecord(e0, s));
     // phase A workspaces and states, one allocation
     Layout LA;
-    std::vector<size_t[8]> oa(nb);
+    std::vector<size_t[9]> oa(nb);
     std::vector<size_t> baseA(nb);
     for (size_t k = 0; k < nb; ++k) {
       Layout L;
@@ -425,7 +431,8 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.code = (uint8_t *)(b + oa[k][1] + 2 * (size_t)fd.n);
       fd.cpbits = (unsigned long long *)(b + oa[k][2]);
       fd.cpoff = (uint32_t *)(b + oa[k][3]);
-      fd.req = (uint16_t *)(b + oa[k][4]);
+      fd.tbits = (uint32_t *)(b + oa[k][4]);
+      fd.bdirty = (uint8_t *)(b + oa[k][8]);
       fd.rank_of = (uint32_t *)(b + oa[k][5]);
       uint8_t *cnt_io = fields[mem[k].index].cnt_io;
       fd.cnt = cnt_io ? cnt_io : (uint8_t *)(b + oa[k][6]);
@@ -590,6 +597,7 @@ exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, ex
     fd.tiles_y = (fd.ny + fd.tile_y - 1) / fd.tile_y;
     fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
     fd.ntiles = fd.tiles_x * fd.tiles_y * fd.tiles_z;
+    fd.frontier = 0;  // batched check passes cover every box
     st = setup_field(ctx, fd, field->f, field->g_hat, field->g_out, field->cnt_io,
                      field->params.max_iters, job->A, job->B, (hipStream_t)stream);
   }
@@ -613,7 +621,7 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   HIP_OR_FAIL_B(hipSetDevice(ctx->device));
   const size_t nf = (size_t)njobs;
   const size_t lw = list_words(nf);
-  const size_t bytes = nf * sizeof(FieldDev) + 4 * lw * sizeof(uint32_t);
+  const size_t bytes = nf * sizeof(FieldDev) + NLISTS * lw * sizeof(uint32_t);
   // staging of the previous step must have been consumed before reuse
   if (ctx->step_copied) HIP_OR_FAIL_B(hipEventSynchronize(ctx->step_copied));
   else HIP_OR_FAIL_B(hipEventCreateWithFlags(&ctx->step_copied, hipEventDisableTiming));
@@ -630,8 +638,8 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   FieldDev *hf = (FieldDev *)ctx->step_host;
   uint32_t *hl = (uint32_t *)(hf + nf);
   std::vector<int> f3, f2, fc, fa;
-  std::vector<uint32_t> i3, i2, ic, ia;
-  uint64_t boxes = 0, cps = 0;
+  std::vector<uint32_t> i3, i2, ic, ia, iw;
+  uint64_t boxes = 0, cps = 0, words = 0;
   for (size_t k = 0; k < nf; ++k) {
     if (!jobs[k]) return fail_b(ctx, EXZ_E_INVALID, "null job");
     hf[k] = jobs[k]->fd;
@@ -642,16 +650,19 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
     ic.push_back(fd.K > 1 ? (uint32_t)(fd.K - 1) : 0u);
     fa.push_back((int)k);
     ia.push_back(1);
+    iw.push_back(apply_items(fd));
+    words += apply_items(fd);
     boxes += (uint64_t)fd.ntiles;
     cps += fd.K > 1 ? (uint64_t)(fd.K - 1) : 0;
     jobs[k]->last = s;
   }
-  Lists L[4];
+  Lists L[NLISTS];
   L[0].build(f3, i3);
   L[1].build(f2, i2);
   L[2].build(fc, ic);
   L[3].build(fa, ia);
-  for (int q = 0; q < 4; ++q) std::memcpy(hl + q * lw, L[q].v.data(), L[q].v.size() * 4);
+  L[4].build(fa, iw);
+  for (int q = 0; q < NLISTS; ++q) std::memcpy(hl + q * lw, L[q].v.data(), L[q].v.size() * 4);
   FieldDev *df = (FieldDev *)ctx->step_dev;
   uint32_t *dl = (uint32_t *)(df + nf);
   HIP_OR_FAIL_B(hipMemcpyAsync(df, hf, bytes, hipMemcpyHostToDevice, s));
@@ -659,7 +670,8 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   BatchShape shape;  // jobs use the default boxes (3D 4 x 4, 2D 16 x 1)
   const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(boxes, 256 * 8));
   const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>((cps + 255) / 256, 256 * 8));
-  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, grid_cp, (int)nf, s);
+  const int grid_apply = (int)std::max<uint64_t>(1, std::min<uint64_t>(words, 256 * 16));
+  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, grid_cp, (int)nf, grid_apply, s);
   HIP_OR_FAIL_B(hipGetLastError());
   return EXZ_OK;
 }

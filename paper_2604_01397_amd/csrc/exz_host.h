@@ -33,7 +33,7 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
                             uint8_t *cnt_io, const exz_params *params, exz_result *res,
                             hipStream_t s);
 void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, Layout &L,
-              size_t off[8]);
+              size_t off[9]);
 void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]);
 hipError_t launch_iota(uint32_t *v, uint32_t n, hipStream_t s);
 void layout_c(const FieldDev &fd, bool original, bool certify, Layout &L, size_t off[6]);
@@ -52,6 +52,7 @@ struct exz_ctx {
   int tile_y = 4;
   int tile_z = 4;
   int grid_blocks = -1;
+  bool frontier = true;
   std::string last_error;
   uint8_t *d_comp = nullptr;        // link component table (2^14 bytes)
   uint32_t *d_conn = nullptr;       // one-component bits (2^14 bits)

@@ -45,6 +45,7 @@ struct State {
   uint32_t cert_bad;   // certificate mismatches
   uint32_t shard[5][64];  // per-iteration counters of the apply pass, sharded by block
   uint32_t nsaddle;       // saddles of f (original mode)
+  int32_t dense;          // the next check covers every box (first pass, fixpoint confirmation)
   uint32_t jump[MAX_JUMP_ROUNDS];  // pointer-jumping round flags
   int64_t iterations;
   int64_t edit_ops;
@@ -53,7 +54,8 @@ struct State {
   int64_t edited_total;
   int64_t residual;
   int64_t max_iters;
-  int64_t pad[2];
+  int64_t passes;                 // check passes that ran (profiling)
+  unsigned long long checked;     // vertices those passes checked (profiling)
 };
 
 // Everything a kernel needs to work on one field.  Passed by value to the
@@ -72,6 +74,7 @@ struct FieldDev {
   int32_t ntiles;            // tiles_x * tiles_y * tiles_z
   int32_t grid_blocks;       // stencil grid: 0 one block per box, < 0 persistent default, > 0 fixed
   int32_t trace_cap;
+  int32_t frontier;     // 1: re-check only boxes whose closed neighbourhood changed
   int32_t dlt[16];      // linear index offset of each slot (dlt[SELF] = 0)
   double xiT, delta;    // in the field type, widened exactly to double
   const void *f;
@@ -90,13 +93,20 @@ struct FieldDev {
   uint32_t *sel_f;      // 2 per saddle: selections in f (join, split) or ~0
   uint32_t *lab;        // 2n: g's descent / ascent labels (original mode)
   uint32_t *lab_f;      // 2n: f's resolved path termini (original mode, certificate)
-  uint16_t *req;        // n: decrease requests of each vertex (slot mask, bit SELF = itself)
+  uint32_t *tbits;      // 2 * nchunk words: the target set of the iteration, one bit per vertex
+  uint8_t *bdirty;      // ntiles: boxes whose closed neighbourhood the last apply changed
   int64_t *trace;       // 2 * trace_cap (|S|, changed) per iteration, nullable
   State *st;
 };
 
 // ---------------------------------------------------------------------------
 // device helpers
+
+// Adds vertex t to the target set (one bit per vertex; several checks may
+// name the same target, the set keeps it once).
+__device__ __forceinline__ void mark_target(uint32_t *bits, uint32_t t) {
+  atomicOr(bits + (t >> 5), 1u << (t & 31u));
+}
 
 // Simulation of Simplicity: (a, ia) < (b, ib).  Bitwise, not short-circuit,
 // so that the compiler emits straight-line compares instead of branches.

@@ -52,15 +52,53 @@ __device__ __forceinline__ BoxWalk box_walk(const FieldDev &fd) {
 
 template <class T, int TY, int TZ>
 __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *__restrict__ conn) {
-  if (fd.st->done) return;
+  State *st = fd.st;
+  if (st->done) return;
   __shared__ T S[Box<TY, TZ>::NE];
+  __shared__ unsigned long long pick;
   StageMap<TY, TZ> m;
   stage_map<TY, TZ>(fd, threadIdx.y * 64 + threadIdx.x, m);
   const BoxWalk w = box_walk(fd);
-  for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
-    check_box<T, TY, TZ>(fd, conn, box_of(fd, tile, TY, TZ), S, m);
-    __syncthreads();
+  const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+  uint32_t done_v = 0;  // vertices checked by this work-group (lead thread)
+  if (!fd.frontier || st->dense) {
+    for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
+      const BoxOrigin o = box_of(fd, tile, TY, TZ);
+      check_box<T, TY, TZ>(fd, conn, o, S, m);
+      if (lead) done_v += box_vertices(fd, o, TY, TZ);
+      __syncthreads();
+    }
+  } else {
+    // Frontier pass: a box none of whose cells (halo included) changed in
+    // the last apply would name the same targets as at its last check, and
+    // those were all blocked then and still are, so only dirty boxes are
+    // checked.  The first wave reads (and clears) the flags of the block's
+    // next 64 boxes.
+    for (uint32_t t0 = w.first; t0 < w.end; t0 += 64u * w.stride) {
+      if (threadIdx.y == 0) {
+        const uint32_t tile = t0 + threadIdx.x * w.stride;
+        bool d = false;
+        if (tile < w.end) {
+          d = fd.bdirty[tile] != 0;
+          if (d) fd.bdirty[tile] = 0;
+        }
+        const unsigned long long b = __ballot(d);
+        if (threadIdx.x == 0) pick = b;
+      }
+      __syncthreads();
+      unsigned long long b = pick;
+      __syncthreads();  // pick is rewritten for the next 64 boxes
+      while (b) {
+        const uint32_t k = (uint32_t)(__ffsll(b) - 1);
+        b &= b - 1;
+        const BoxOrigin o = box_of(fd, t0 + k * w.stride, TY, TZ);
+        check_box<T, TY, TZ>(fd, conn, o, S, m);
+        if (lead) done_v += box_vertices(fd, o, TY, TZ);
+        __syncthreads();
+      }
+    }
   }
+  if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
 }
 
 template <class T>
@@ -70,19 +108,14 @@ __global__ void __launch_bounds__(256) k_cpcmp(FieldDev fd) {
   if (k + 1 < (uint32_t)fd.K) cp_pair<T>(fd, k);
 }
 
-template <class T, int TY, int TZ>
-__global__ void __launch_bounds__(64 * TY) k_apply(FieldDev fd) {
+// ApplyBoundedEdits over the target bitmask, one thread per 32-vertex word.
+template <class T>
+__global__ void __launch_bounds__(APPLY_BLOCK) k_apply(FieldDev fd) {
   if (fd.st->done) return;
-  __shared__ uint16_t Q[Box<TY, TZ>::NE];
-  StageMap<TY, TZ> m;
-  stage_map<TY, TZ>(fd, threadIdx.y * 64 + threadIdx.x, m);
-  const BoxWalk w = box_walk(fd);
+  const uint32_t w = blockIdx.x * APPLY_BLOCK + threadIdx.x;
   EditCount ec = {{0, 0, 0, 0, 0}};
-  for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
-    apply_box<T, TY, TZ>(fd, box_of(fd, tile, TY, TZ), Q, ec, m);
-    __syncthreads();
-  }
-  flush_counts<TY>(fd.st, ec, blockIdx.x);
+  if (w < (uint32_t)(2 * fd.nchunk)) apply_word<T>(fd, w, ec);
+  flush_counts<APPLY_BLOCK / 64>(fd.st, ec, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(64) k_finalize(FieldDev fd) { finalize_field(fd); }
@@ -97,9 +130,12 @@ __global__ void __launch_bounds__(64) k_state_reset(State *st, int64_t max_iters
   st->ntargets = st->changed = st->lossless = st->floored = st->first = 0;
   st->cert_bad = 0;
   st->nsaddle = 0;
+  st->dense = 1;
   st->iterations = st->edit_ops = st->lossless_total = st->floor_total = st->edited_total = 0;
   st->residual = 0;
   st->max_iters = max_iters;
+  st->passes = 0;
+  st->checked = 0;
 }
 
 hipError_t launch_state_reset(const FieldDev &fd, int64_t max_iters, hipStream_t s) {
@@ -141,11 +177,8 @@ static void launch_check_cpcmp(const FieldDev &fd, const uint32_t *conn, const u
 
 template <class T>
 static void launch_apply(const FieldDev &fd, hipStream_t s) {
-#define EXZ_BOX_APPLY(a, b)                                                                \
-  if (fd.tile_y == a && fd.tile_z == b)                                                    \
-    hipLaunchKernelGGL((k_apply<T, a, b>), dim3(persistent_grid(fd)), dim3(64, a), 0, s, fd);
-  EXZ_BOX_SHAPES(EXZ_BOX_APPLY)
-#undef EXZ_BOX_APPLY
+  const int grid = (2 * fd.nchunk + APPLY_BLOCK - 1) / APPLY_BLOCK;
+  hipLaunchKernelGGL(k_apply<T>, dim3(grid), dim3(APPLY_BLOCK), 0, s, fd);
 }
 
 template <class T>
@@ -180,15 +213,7 @@ __global__ void k_targets_to_bytes(FieldDev fd, uint8_t *out) {
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   bool hit = false;
   if (t < (uint32_t)fd.n) {
-    const int x = (int)(t % (uint32_t)fd.nx);
-    const uint32_t r = t / (uint32_t)fd.nx;
-    const int y = (int)(r % (uint32_t)fd.ny);
-    const int z = (int)(r / (uint32_t)fd.ny);
-    const uint32_t vm = valid_slots(x, y, z, fd.nx, fd.ny, fd.nz);
-    uint32_t h = (fd.req[t] >> SELF) & 1u;
-    for (int s = 0; s < NSLOT; ++s)
-      if ((vm >> (s ^ 1)) & 1u) h |= (fd.req[t - fd.dlt[s]] >> s) & 1u;
-    hit = h != 0;
+    hit = ((fd.tbits[t >> 5] >> (t & 31u)) & 1u) != 0;
     out[t] = hit;
   }
   const uint32_t c = wave_sum((uint32_t)hit);

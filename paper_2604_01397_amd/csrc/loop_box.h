@@ -180,8 +180,26 @@ __device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint3
   return req;
 }
 
-// CheckConstraints on one box: stage g, write the request mask of every
-// vertex (and, in original mode, g's descent / ascent pointers).
+// Adds the targets named by vertex i's request mask r (bit s: the neighbour
+// in slot s, bit SELF: i itself).
+__device__ __forceinline__ void post_targets(const FieldDev &fd, uint32_t i, uint32_t r) {
+  if ((r >> SELF) & 1u) mark_target(fd.tbits, i);
+  r &= LOW_MASK;
+  while (r) {
+    const int s = __ffs(r) - 1;
+    r &= r - 1;
+    mark_target(fd.tbits, (uint32_t)((int)i + fd.dlt[s]));
+  }
+}
+
+// Vertices of the box inside the domain.
+__device__ __forceinline__ uint32_t box_vertices(const FieldDev &fd, BoxOrigin o, int TY, int TZ) {
+  return (uint32_t)(min(64, fd.nx - o.x0) * min(TY, fd.ny - o.y0) * min(TZ, fd.nz - o.z0));
+}
+
+// CheckConstraints on one box: stage g, add the targets every vertex names
+// to the target set (and, in original mode, write g's descent / ascent
+// pointers).
 template <class T, int TY, int TZ>
 __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__restrict__ conn,
                                           BoxOrigin o, T *S, const StageMap<TY, TZ> &m) {
@@ -211,8 +229,9 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__
       const uint32_t i = i0 + k * plane;
       const T *c = S + (k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1;
       uint32_t av = 0, dv = 0;
-      fd.req[i] = (uint16_t)check_vertex<T>(fd, conn, c, -B::PLANE, B::PLANE, x, y, z, i,
-                                             codes[k], lows[k], av, dv, interior);
+      const uint32_t r = check_vertex<T>(fd, conn, c, -B::PLANE, B::PLANE, x, y, z, i, codes[k],
+                                         lows[k], av, dv, interior);
+      if (r) post_targets(fd, i, r);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
         fd.lab[i] = dv;
         fd.lab[fd.n + i] = (uint32_t)fd.n + av;
@@ -223,34 +242,20 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__
 
 // Reformulated event constraints: consecutive critical points in f's order
 // must keep their order in g; an inverted pair decreases the lower one.
-// Rank r maps to a distinct vertex, so the read-modify-write of its request
-// word races with nothing.
+// Values are finite, so b > a settles most pairs without the vertex indices.
 template <class T>
 __device__ __forceinline__ void cp_pair(const FieldDev &fd, uint32_t r) {
   const T *V = (const T *)fd.cp_val;
   const T a = V[r], b = V[r + 1];
+  if (b > a) return;
   const uint32_t ia = fd.cp_idx[r], ib = fd.cp_idx[r + 1];
-  if (sos_lt(b, ib, a, ia)) fd.req[ia] = (uint16_t)(fd.req[ia] | (1u << SELF));
+  if (sos_lt(b, ib, a, ia)) mark_target(fd.tbits, ia);
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
   return v;
-}
-
-// Is the vertex whose LDS request word is Q[0] requested by itself or by a
-// neighbour?  Neighbour i = t - d(s) asks for t when bit s of its mask is
-// set; i lies in the domain exactly when the opposite slot s^1 is valid at t.
-// (Cells outside the domain were staged as 0: they request nothing.)
-__device__ __forceinline__ bool requested(const uint16_t *Q, int qm, int qp) {
-  uint32_t hit = Q[0] >> SELF;
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const int po = DZS[s] > 0 ? qm : DZS[s] < 0 ? qp : 0;  // plane of z - dz
-    hit |= (uint32_t)Q[po - DYS[s] * HALO_W - DXS[s]] >> s;
-  }
-  return (hit & 1u) != 0;
 }
 
 // ApplyBoundedEdits: each target moves once, from its own value, by one step
@@ -261,69 +266,61 @@ struct EditCount {
   uint32_t v[5];  // targets, changed, lossless, floored, first edits
 };
 
-// ApplyBoundedEdits on one box; adds this thread's counts to ec.  Target
-// flags come first (LDS only), then every load the targets need is issued
-// together, then the edits: one global round trip per box, not per vertex.
-template <class T, int TY, int TZ>
-__device__ __forceinline__ void apply_box(const FieldDev &fd, BoxOrigin o, uint16_t *Q,
-                                          EditCount &ec, const StageMap<TY, TZ> &m) {
-  using B = Box<TY, TZ>;
-  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx;
-  const int x = o.x0 + lx, y = o.y0 + ly;
-  const bool col = x < fd.nx && y < fd.ny;
-  const uint32_t plane = (uint32_t)fd.nx * (uint32_t)fd.ny;
-  const uint32_t i0 = (uint32_t)x + (uint32_t)fd.nx * ((uint32_t)y + (uint32_t)fd.ny * (uint32_t)o.z0);
+// Marks every box whose check reads vertex t (the box plus its one-cell
+// halo contains t), so the next frontier check visits it.
+__device__ __forceinline__ void mark_boxes(const FieldDev &fd, uint32_t t) {
+  const uint32_t x = t % (uint32_t)fd.nx, r = t / (uint32_t)fd.nx;
+  const uint32_t y = r % (uint32_t)fd.ny, z = r / (uint32_t)fd.ny;
+  const uint32_t ty = (uint32_t)fd.tile_y, tz = (uint32_t)fd.tile_z;
+  const uint32_t bx0 = x ? (x - 1) >> 6 : 0, bx1 = min((x + 1) >> 6, (uint32_t)fd.tiles_x - 1);
+  const uint32_t by0 = y ? (y - 1) / ty : 0, by1 = min((y + 1) / ty, (uint32_t)fd.tiles_y - 1);
+  const uint32_t bz0 = z ? (z - 1) / tz : 0, bz1 = min((z + 1) / tz, (uint32_t)fd.tiles_z - 1);
+  for (uint32_t bz = bz0; bz <= bz1; ++bz)
+    for (uint32_t by = by0; by <= by1; ++by)
+      for (uint32_t bx = bx0; bx <= bx1; ++bx)
+        fd.bdirty[bx + (uint32_t)fd.tiles_x * (by + (uint32_t)fd.tiles_y * bz)] = 1;
+}
+
+// ApplyBoundedEdits on the 32 vertices of target word w; clears the word
+// and adds this thread's counts to ec.  In frontier mode every vertex whose
+// value or count moved marks the boxes that read it.
+template <class T>
+__device__ __forceinline__ void apply_word(const FieldDev &fd, uint32_t w, EditCount &ec) {
+  uint32_t bits = fd.tbits[w];
+  if (!bits) return;
+  fd.tbits[w] = 0;
+  ec.v[0] += (uint32_t)__popc(bits);
   T *G = (T *)fd.g;
   const T *F = (const T *)fd.f;
   const T xiT = (T)fd.xiT, delta = (T)fd.delta;
-  stage_box<TY, TZ>(fd, (const uint16_t *)fd.req, Q, o, tid, m);
-  __syncthreads();
-  bool hit[TZ];
-  bool any = false;
-#pragma unroll
-  for (int k = 0; k < TZ; ++k) {
-    hit[k] = col && o.z0 + k < fd.nz &&
-             requested(Q + (k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1, -B::PLANE, B::PLANE);
-    any |= hit[k];
-  }
-  // A wave with no target in its columns skips the edit; otherwise all the
-  // loads its targets need go out together (non-target lanes read their own
-  // vertex or vertex 0, which is always valid).
-  if (!__any(any)) return;
-  T g0[TZ], fv[TZ];
-  uint32_t c0[TZ], rk[TZ];
-#pragma unroll
-  for (int k = 0; k < TZ; ++k) {
-    const uint32_t t = hit[k] ? i0 + k * plane : 0u;
-    g0[k] = G[t];
-    fv[k] = F[t];
-    c0[k] = fd.cnt[t];
-    rk[k] = fd.rank_of[t];
-  }
-#pragma unroll
-  for (int k = 0; k < TZ; ++k) {
-    if (!hit[k]) continue;
-    const uint32_t t = i0 + k * plane;
-    ++ec.v[0];
-    const T L = lower_bound(fv[k], xiT);
-    if (g0[k] == L) continue;  // at the floor: blocked
-    const uint32_t c = c0[k] + 1;
+  while (bits) {
+    const uint32_t t = w * 32u + (uint32_t)(__ffs(bits) - 1);
+    bits &= bits - 1;
+    const T g0 = G[t], fv = F[t];
+    const uint32_t c0 = fd.cnt[t], rk = fd.rank_of[t];
+    const T L = lower_bound(fv, xiT);
+    if (g0 == L) continue;  // at the floor: blocked
+    const uint32_t c = c0 + 1;
     fd.cnt[t] = (uint8_t)c;
     T v;
     if (c > (uint32_t)fd.N) {
       v = L;  // (N+1)-th edit: store the lower bound itself
       ++ec.v[2];
     } else {
-      const T cand = g0[k] - delta;
+      const T cand = g0 - delta;
       v = cand < L ? L : cand;
     }
     G[t] = v;
-    if (rk[k] != 0xFFFFFFFFu) ((T *)fd.cp_val)[rk[k]] = v;
+    if (rk != 0xFFFFFFFFu) ((T *)fd.cp_val)[rk] = v;
     ++ec.v[1];
     ec.v[3] += v == L;
     ec.v[4] += c == 1;
+    if (fd.frontier) mark_boxes(fd, t);
   }
 }
+
+// Work-group size of the apply passes (threads, one target word each).
+constexpr int APPLY_BLOCK = 256;
 
 // Block reduction of the edit counts, added to one of the field's 64 shards.
 template <int TY>
@@ -348,6 +345,7 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
   State *st = fd.st;
   if (st->done) return;
   const int lane = threadIdx.x;
+  if (lane == 0) st->passes += 1;
   uint32_t v[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -360,12 +358,18 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
     fd.trace[2 * st->iterations] = nt;
     fd.trace[2 * st->iterations + 1] = ch;
   }
-  if (nt == 0) {
+  if (ch == 0 && fd.frontier && !st->dense) {
+    // A frontier pass skips boxes whose requests were all blocked, so it
+    // cannot tell a fixpoint from convergence (or count the residual): one
+    // dense pass over the unchanged field settles it.
+    st->dense = 1;
+  } else if (nt == 0) {
     st->done = CONVERGED;
   } else if (ch == 0) {
     st->done = STUCK;
     st->residual = nt;
   } else {
+    st->dense = 0;
     st->iterations += 1;
     st->edit_ops += ch;
     st->lossless_total += v[2];

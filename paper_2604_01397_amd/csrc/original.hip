@@ -133,13 +133,6 @@ __global__ void k_select_f(FieldDev fd, const uint8_t *comp) {
   fd.sel_f[2 * k + 1] = comp[upper] >= 2 ? select_extremum(fd, F, fd.lab_f, s, upper, false) : NONE;
 }
 
-// Set the self-request bit of vertex t (32-bit atomic on the word holding
-// its 16-bit request mask: several saddles may pick the same extremum).
-__device__ __forceinline__ void request_self(uint16_t *req, uint32_t t) {
-  uint32_t *w = (uint32_t *)req + (t >> 1);
-  atomicOr(w, (1u << SELF) << ((t & 1u) * 16u));
-}
-
 template <class T>
 __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   const State *st = fd.st;
@@ -155,7 +148,7 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   // C2: saddle order
   if (k + 1 < ns) {
     const uint32_t rn = fd.sad_rank[k + 1];
-    if (sos_lt(V[rn], fd.cp_idx[rn], V[rk], s)) request_self(fd.req, s);
+    if (sos_lt(V[rn], fd.cp_idx[rn], V[rk], s)) mark_target(fd.tbits, s);
   }
   // C3: selected extrema along the integral paths of g
   const uint32_t mf = fd.sel_f[2 * k], Mf = fd.sel_f[2 * k + 1];
@@ -172,12 +165,12 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   }
   if (mf != NONE && glower) {
     const uint32_t mg = select_extremum(fd, G, fd.lab, s, glower, true);
-    if (mg != mf) request_self(fd.req, sos_lt(F[mg], mg, F[mf], mf) ? mg : mf);
+    if (mg != mf) mark_target(fd.tbits, sos_lt(F[mg], mg, F[mf], mf) ? mg : mf);
   }
   const uint32_t gupper = vm & ~glower;
   if (Mf != NONE && gupper) {
     const uint32_t Mg = select_extremum(fd, G, fd.lab, s, gupper, false);
-    if (Mg != Mf) request_self(fd.req, sos_lt(F[Mg], Mg, F[Mf], Mf) ? Mg : Mf);
+    if (Mg != Mf) mark_target(fd.tbits, sos_lt(F[Mg], Mg, F[Mf], Mf) ? Mg : Mf);
   }
 }
 

@@ -41,7 +41,7 @@ class Result(ctypes.Structure):
                 ("num_critical", ctypes.c_int64), ("status", ctypes.c_int32),
                 ("certified", ctypes.c_int32), ("setup_ms", ctypes.c_double),
                 ("loop_ms", ctypes.c_double), ("check_launches", ctypes.c_int64),
-                ("check_ms", ctypes.c_double)]
+                ("check_ms", ctypes.c_double), ("check_vertices", ctypes.c_int64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -238,6 +238,45 @@ class Context:
             raise ExactzError(st, self.last_error())
         return [(outs[k][0], outs[k][1], res[k].to_dict()) for k in range(n)]
 
+    # ------------------------------------------------------------------
+    # serving primitives: jobs whose state stays on the device between steps
+
+    def job_create(self, f, g_hat, xi, n_steps=5, max_iters=0, g_out=None, cnt=None,
+                   stream=None):
+        """Validate a field and build its reference topology; returns a Job.
+
+        The job keeps references to its tensors until it is released.
+        ``g_out`` may be ``g_hat`` (in place)."""
+        import torch
+        _check_tensor(f)
+        _check_tensor(g_hat, f)
+        if g_out is None:
+            g_out = torch.empty_like(f)
+        _check_tensor(g_out, f)
+        if cnt is None:
+            cnt = torch.zeros(f.shape, dtype=torch.uint8, device=f.device)
+        fl = Field()
+        fl.params = make_params(f, xi, n_steps, REFORMULATED, max_iters)
+        fl.f = f.data_ptr()
+        fl.g_hat = g_hat.data_ptr()
+        fl.g_out = g_out.data_ptr()
+        fl.cnt_io = cnt.data_ptr()
+        h = ctypes.c_void_p()
+        st = self.lib.exz_job_create(self.h, ctypes.byref(fl), _stream_ptr(stream), ctypes.byref(h))
+        if st != OK:
+            raise ExactzError(st, self.last_error())
+        return Job(self, h, (f, g_hat, g_out, cnt))
+
+    def step(self, jobs, iters=1, stream=None):
+        """Advance every listed job by up to ``iters`` rounds (stream-ordered)."""
+        n = len(jobs)
+        if n == 0:
+            return
+        arr = (ctypes.c_void_p * n)(*[j.h for j in jobs])
+        st = self.lib.exz_step(self.h, arr, n, int(iters), _stream_ptr(stream))
+        if st != OK:
+            raise ExactzError(st, self.last_error())
+
     def debug_bounds(self, f, xi, stream=None):
         import torch
         _check_tensor(f)
@@ -264,6 +303,50 @@ class Context:
         if st != OK:
             raise ExactzError(st, self.last_error())
         return mark.bool(), cnt.value
+
+
+class Job:
+    """A correction job resident on the device (see Context.job_create)."""
+
+    def __init__(self, ctx, handle, tensors):
+        self.ctx = ctx
+        self.h = handle
+        self.f, self.g_hat, self.g_out, self.cnt = tensors
+
+    def poll(self):
+        """(done, result dict); waits for the work issued for this job."""
+        done = ctypes.c_int32()
+        r = Result()
+        st = self.ctx.lib.exz_job_poll(self.h, ctypes.byref(done), ctypes.byref(r))
+        if st != OK:
+            raise ExactzError(st, self.ctx.last_error())
+        return bool(done.value), r.to_dict()
+
+    def release(self):
+        if self.h:
+            self.ctx.lib.exz_job_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def job_bytes(shape_xyz, dtype=F32, xi=1e-3, n_steps=5):
+    """exz_job_bytes: device workspace of a job on a (nx[, ny[, nz]]) field."""
+    lib = load()
+    p = Params()
+    p.ndim = len(shape_xyz)
+    p.dtype = dtype
+    d = list(shape_xyz) + [1] * (3 - len(shape_xyz))
+    for k in range(3):
+        p.dims[k] = int(d[k])
+    p.xi = xi
+    p.n_steps = n_steps
+    p.event_mode = REFORMULATED
+    return int(lib.exz_job_bytes(ctypes.byref(p)))
 
 
 def workspace_bytes(shape_xyz, dtype=F32, xi=1e-3, n_steps=5, mode=REFORMULATED, certify=False):

@@ -1,0 +1,216 @@
+"""Continuous-batching correction server on one GPU.
+
+Jobs arrive over time.  The server admits a job once its device footprint
+(the job workspace plus its field, output and count buffers) fits the HBM
+budget, materialises its inputs and builds its reference topology on a
+side stream while the admitted jobs keep iterating, advances every active
+job together with one batched step per tick (``exz_step``: shared launches,
+per-job state, per-job convergence), retires finished jobs, frees their
+memory and admits the next ones.  Admission is first come, first served;
+a job larger than the whole budget is rejected.
+
+Latency of a job = its completion (result polled, corrected field on the
+device) minus its arrival; aggregate throughput = field bytes of all
+completed jobs over the time from the first arrival to the last
+completion.
+
+The scheduling loop is plain host logic over an executor interface
+(``footprint / start / step / poll / finish``), so it is tested on the CPU
+with a simulated executor; ``DeviceExecutor`` drives the library.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Optional
+
+import numpy as np
+
+
+@dataclass
+class JobSpec:
+    """One request: when it arrives and how to materialise its inputs."""
+    job_id: int
+    arrival: float                 # seconds after the start of the trace
+    shape: tuple                   # C-order shape of the field
+    field_bytes: int               # n * bytes per value
+    make: Optional[Callable[[Any], tuple]] = None  # stream -> (f, g_hat, xi) on the device
+    meta: dict = field(default_factory=dict)
+
+
+@dataclass
+class JobRecord:
+    spec: JobSpec
+    admitted: float = float("nan")
+    completed: float = float("nan")
+    result: Optional[dict] = None
+    outputs: Optional[tuple] = None
+    error: Optional[str] = None
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.spec.arrival
+
+
+@dataclass
+class Report:
+    records: list
+    wall: float
+    max_active: int
+    max_bytes: int
+    steps: int
+
+    def completed(self):
+        return [r for r in self.records if r.error is None and not np.isnan(r.completed)]
+
+    def summary(self) -> dict:
+        done = self.completed()
+        lat = np.array([r.latency for r in done]) if done else np.zeros(0)
+        first = min((r.spec.arrival for r in self.records), default=0.0)
+        last = max((r.completed for r in done), default=first)
+        span = max(last - first, 1e-12)
+        nbytes = sum(r.spec.field_bytes for r in done)
+        return {
+            "jobs": len(self.records),
+            "completed": len(done),
+            "rejected": sum(r.error is not None for r in self.records),
+            "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "mean_latency_s": float(lat.mean()) if lat.size else None,
+            "throughput_GBps": nbytes / span / 1e9,
+            "field_GB": nbytes / 1e9,
+            "span_s": span,
+            "max_active": self.max_active,
+            "max_resident_GB": self.max_bytes / 1e9,
+            "steps": self.steps,
+        }
+
+
+class Server:
+    """The scheduling loop (see the module docstring).
+
+    ``executor`` provides ``footprint(spec) -> bytes``, ``start(spec) ->
+    handle``, ``step(handles, iters)``, ``poll(handle) -> (done, result)`` and
+    ``finish(handle) -> outputs``.
+    """
+
+    def __init__(self, executor, budget_bytes: int, max_active: int = 64,
+                 iters_per_step: int = 2, clock=time.perf_counter, sleep=time.sleep,
+                 keep_outputs: bool = False):
+        if budget_bytes <= 0 or max_active < 1 or iters_per_step < 1:
+            raise ValueError("budget, max_active and iters_per_step must be positive")
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.iters = int(iters_per_step)
+        self.clock = clock
+        self.sleep = sleep
+        self.keep_outputs = keep_outputs
+
+    def run(self, specs) -> Report:
+        pending = collections.deque(sorted(specs, key=lambda s: (s.arrival, s.job_id)))
+        queue = collections.deque()
+        active = []          # (record, handle, footprint)
+        records = {s.job_id: JobRecord(s) for s in pending}
+        used = 0
+        max_active = max_bytes = steps = 0
+        t0 = self.clock()
+        while pending or queue or active:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            # the batched step of the active jobs goes out first, so the
+            # set-up of newly admitted jobs overlaps it on the device
+            if active:
+                self.ex.step([h for _, h, _ in active], self.iters)
+                steps += 1
+            while queue and len(active) < self.max_active:
+                spec = queue[0]
+                need = int(self.ex.footprint(spec))
+                if need > self.budget:
+                    queue.popleft()
+                    records[spec.job_id].error = "footprint %d B exceeds the budget" % need
+                    continue
+                if used + need > self.budget:
+                    break
+                queue.popleft()
+                rec = records[spec.job_id]
+                rec.admitted = self.clock() - t0
+                try:
+                    h = self.ex.start(spec)
+                except Exception as e:  # a bad request must not stop the server
+                    rec.error = "%s: %s" % (type(e).__name__, e)
+                    continue
+                used += need
+                active.append((rec, h, need))
+            max_active = max(max_active, len(active))
+            max_bytes = max(max_bytes, used)
+            if not active:
+                if pending and not queue:
+                    self.sleep(max(0.0, min(pending[0].arrival - (self.clock() - t0), 0.05)))
+                continue
+            still = []
+            for rec, h, need in active:
+                done, res = self.ex.poll(h)
+                if done:
+                    rec.completed = self.clock() - t0
+                    rec.result = res
+                    out = self.ex.finish(h)
+                    if self.keep_outputs:
+                        rec.outputs = out
+                    used -= need
+                else:
+                    still.append((rec, h, need))
+            active = still
+        wall = self.clock() - t0
+        return Report([records[k] for k in sorted(records)], wall, max_active, max_bytes, steps)
+
+
+class DeviceExecutor:
+    """Runs jobs through the library's job API on one device.
+
+    Inputs are materialised by ``spec.make(stream)`` on a side stream, then
+    the job is created there (its set-up overlaps the batched steps issued
+    on the main stream); the corrected field is written in place over the
+    job's copy of g_hat.
+    """
+
+    def __init__(self, ctx, n_steps: int = 5, keep_outputs: bool = False):
+        import torch
+
+        from . import exactz
+        self.torch = torch
+        self.exactz = exactz
+        self.ctx = ctx
+        self.n_steps = n_steps
+        self.keep = keep_outputs
+        self.main = torch.cuda.Stream()
+        self.side = torch.cuda.Stream()
+
+    def footprint(self, spec) -> int:
+        shape_xyz = tuple(reversed(spec.shape))
+        n = int(np.prod(spec.shape))
+        b = spec.field_bytes // max(n, 1)
+        work = self.exactz.job_bytes(shape_xyz, self.exactz.F32 if b == 4 else self.exactz.F64,
+                                     n_steps=self.n_steps)
+        return work + 2 * spec.field_bytes + n  # f, g (in place), counts
+
+    def start(self, spec):
+        with self.torch.cuda.stream(self.side):
+            f, g, xi = spec.make(self.side)
+            cnt = self.torch.zeros(f.shape, dtype=self.torch.uint8, device=f.device)
+        job = self.ctx.job_create(f, g, xi, n_steps=self.n_steps, g_out=g, cnt=cnt,
+                                  stream=self.side)
+        return job
+
+    def step(self, handles, iters):
+        self.ctx.step(handles, iters, stream=self.main)
+
+    def poll(self, job):
+        return job.poll()
+
+    def finish(self, job):
+        out = (job.g_out, job.cnt) if self.keep else None
+        job.release()
+        return out

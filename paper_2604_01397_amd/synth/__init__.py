@@ -286,3 +286,66 @@ def config4_specs(njobs: int = 1000, rate: float = 200.0, seed: int = 4,
     edges = np.exp(rng.uniform(math.log(lo), math.log(hi), njobs)).round().astype(int)
     return [{"j": j, "arrival": float(t[j]), "edge": int(edges[j]) + 2,
              "seed": 4000 + j, "rel": 1e-3} for j in range(njobs)]
+
+
+# ----------------------------------------------------------------------------
+# device-side generation for the serving workload (blocks appear in HBM, as
+# an in-situ simulation would leave them); same rules as the host versions
+
+
+def grf3d_device(n: int, seed: int, slope: float, device="cuda:0"):
+    """Periodic GRF (P(k) ~ |k|^slope, zero mean, unit variance) of edge n,
+    float32, synthesised on the device with torch's FFT (seeded)."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    w = torch.randn((n, n, n), generator=gen, device=device, dtype=torch.float32)
+    W = torch.fft.rfftn(w)
+    del w
+    k = torch.fft.fftfreq(n, d=1.0 / n, device=device, dtype=torch.float32)
+    kx = torch.fft.rfftfreq(n, d=1.0 / n, device=device, dtype=torch.float32)
+    for iz in range(n):  # one plane at a time keeps the temporaries small
+        kk = k[iz] ** 2 + k[:, None] ** 2 + kx[None, :] ** 2
+        amp = torch.where(kk > 0, kk.clamp_min(1e-30) ** (slope / 4.0), torch.zeros_like(kk))
+        W[iz] *= amp
+    f = torch.fft.irfftn(W, s=(n, n, n))
+    del W
+    f -= f.mean(dtype=torch.float64).to(torch.float32)
+    sd = f.std()
+    if sd > 0:
+        f /= sd
+    return f.contiguous()
+
+
+def eps_for_device(f, rel: float) -> float:
+    """eps_for() of a device tensor: rel * range, rounded down to f's dtype."""
+    import torch
+
+    lo = float(f.min().double())
+    hi = float(f.max().double())
+    e = rel * (hi - lo)
+    if f.dtype == torch.float32:
+        e32 = np.float32(e)
+        if float(e32) > e:
+            e32 = np.nextafter(e32, np.float32(0))
+        return float(e32)
+    return e
+
+
+def quantize_uniform_device(f, eps: float):
+    """quantize_uniform() of a float32 device tensor (same rounding, same band
+    enforcement: |g - f| <= eps exactly)."""
+    import torch
+
+    if f.dtype != torch.float32:
+        raise TypeError("device quantiser handles float32 blocks")
+    b = 2.0 * eps
+    q = torch.round(f.double() / b) * b  # round half to even, as np.rint
+    g = q.to(torch.float32)
+    for _ in range(8):
+        bad = (g.double() - f.double()).abs() > eps
+        if not bool(bad.any()):
+            return g
+        g = torch.where(bad, torch.nextafter(g, f), g)
+    raise RuntimeError("band enforcement did not converge")

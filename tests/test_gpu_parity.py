@@ -281,3 +281,71 @@ def test_certificate(ctx):
     # without certify the field is left untested
     _, _, r = ctx.correct(f, g, c.xi)
     assert r["certified"] == -1
+
+
+# ----------------------------------------------------------------------------
+# frontier check passes: after the first pass only boxes whose cells changed
+# are re-checked; the outcome must not move by a bit
+
+
+FRONTIER_CASES = [
+    ("gauss2d-150", lambda: synth.case_gauss2d(150, seed=21, rel=1e-3)),
+    ("grf3d-48-lorenzo", lambda: synth.case_grf3d(48, seed=22, rel=1e-4, quantizer="lorenzo")),
+    ("grf3d-(70,33,21)-f64", lambda: synth.case_grf3d((21, 33, 70), seed=23, rel=1e-3,
+                                                       dtype=np.float64)),
+]
+
+
+@pytest.mark.parametrize("name,make", FRONTIER_CASES, ids=[c[0] for c in FRONTIER_CASES])
+def test_frontier_matches_dense_and_oracle(name, make):
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = make()
+    dense = exactz.Context(0, profile=1, frontier=0)
+    front = exactz.Context(0, profile=1, frontier=1)
+    try:
+        f, g = _dev(c.f), _dev(c.g_hat)
+        print("case:", name, "dense", flush=True)
+        gd, cd, rd = dense.correct(f, g, c.xi)
+        print("case:", name, "frontier", flush=True)
+        gf, cf, rf = front.correct(f, g, c.xi)
+        torch.cuda.synchronize()
+        assert torch.equal(gd, gf) and torch.equal(cd, cf)
+        for k in ("status", "iterations", "edited_vertices", "edit_ops", "lossless_vertices",
+                  "floor_vertices", "residual_violations", "num_critical"):
+            assert rd[k] == rf[k], (k, rd[k], rf[k])
+        n = c.f.size
+        passes = rd["iterations"] + (rd["status"] != exactz.W_MAX_ITERS)
+        assert rd["check_vertices"] == passes * n
+        if rd["iterations"] > 3:
+            assert rf["check_vertices"] < rd["check_vertices"], (rf, rd)
+        print("checked vertices: dense %d frontier %d over %d passes" % (
+            rd["check_vertices"], rf["check_vertices"], rf["check_launches"]), flush=True)
+        ro, rc, st, _ = oracle.correct(c.f, c.g_hat, c.xi)
+        assert rf["status"] == st["status"] and rf["residual_violations"] == st["residual_violations"]
+        assert np.array_equal(_bits(gf.cpu().numpy()), _bits(ro))
+        assert np.array_equal(cf.cpu().numpy(), rc)
+    finally:
+        dense.close()
+        front.close()
+
+
+@pytest.mark.parametrize("tile", [101, 202, 801, 1602])
+def test_frontier_box_shapes(ctx, tile):
+    c = synth.case_grf3d((33, 19, 130), seed=24, rel=1e-3)
+    f, g = _dev(c.f), _dev(c.g_hat)
+    ctx.set_option("frontier", 0)
+    try:
+        ref, cref, rref = ctx.correct(f, g, c.xi)
+    finally:
+        ctx.set_option("frontier", 1)
+    ctx.set_option("tile", tile)
+    try:
+        out, cout, r = ctx.correct(f, g, c.xi)
+    finally:
+        ctx.set_option("tile", 404)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref) and torch.equal(cout, cref)
+    assert (r["iterations"], r["status"], r["residual_violations"]) == (
+        rref["iterations"], rref["status"], rref["residual_violations"])

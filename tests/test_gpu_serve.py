@@ -1,0 +1,95 @@
+"""Serving on the GPU: every job's corrected field, edit counts and counters
+are the same when it runs alone and when it runs in the mix of a
+continuous-batching server (bit for bit)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_01397_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    return [
+        synth.case_grf3d(34, seed=31, rel=1e-3),
+        synth.case_grf3d((18, 40, 66), seed=32, rel=1e-3),
+        synth.case_gauss2d(130, seed=33, rel=1e-3),
+        synth.case_grf3d(26, seed=34, rel=1e-2, quantizer="lorenzo"),
+        synth.case_grf3d(50, seed=35, rel=1e-3),
+        synth.case_gauss2d(64, seed=36, rel=1e-4, dtype=np.float64),
+        synth.case_grf3d(20, seed=37, rel=1e-3),
+        synth.case_grf3d(42, seed=38, rel=1e-4),
+    ]
+
+
+def test_served_jobs_equal_alone_runs():
+    from paper_2604_01397_amd import exactz
+    from paper_2604_01397_amd.serve import DeviceExecutor, JobSpec, Server
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cases = _cases()
+    ctx = exactz.Context(0)
+    try:
+        specs = []
+        for j, c in enumerate(cases):
+            def make(stream, c=c):
+                f = torch.from_numpy(np.ascontiguousarray(c.f)).cuda()
+                g = torch.from_numpy(np.ascontiguousarray(c.g_hat)).cuda()
+                return f, g, c.xi
+            specs.append(JobSpec(j, 0.002 * j, c.f.shape, c.f.nbytes, make))
+        ex = DeviceExecutor(ctx, keep_outputs=True)
+        # a budget of about three jobs: later arrivals wait for memory
+        budget = 3 * max(ex.footprint(s) for s in specs)
+        print("serving", len(specs), "jobs, budget", budget, flush=True)
+        rep = Server(ex, budget, max_active=4, iters_per_step=3, keep_outputs=True).run(specs)
+        torch.cuda.synchronize()
+        s = rep.summary()
+        print(s, flush=True)
+        assert s["completed"] == len(cases) and rep.max_active >= 2
+        for r, c in zip(rep.records, cases):
+            print("job", r.spec.job_id, c.name, r.result["iterations"], flush=True)
+            g_srv, c_srv = r.outputs
+            f = torch.from_numpy(np.ascontiguousarray(c.f)).cuda()
+            g = torch.from_numpy(np.ascontiguousarray(c.g_hat)).cuda()
+            g1, c1, r1 = ctx.correct(f, g, c.xi)
+            torch.cuda.synchronize()
+            assert torch.equal(g_srv, g1) and torch.equal(c_srv, c1), c.name
+            for k in ("iterations", "edited_vertices", "edit_ops", "lossless_vertices",
+                      "floor_vertices", "residual_violations", "status"):
+                assert r.result[k] == r1[k], (c.name, k, r.result[k], r1[k])
+        # and one of them against the CPU oracle
+        c = cases[3]
+        go, co, st, _ = oracle.correct(c.f, c.g_hat, c.xi)
+        g_srv, c_srv = rep.records[3].outputs
+        assert np.array_equal(g_srv.cpu().numpy().view(np.uint32), go.view(np.uint32))
+        assert np.array_equal(c_srv.cpu().numpy(), co)
+    finally:
+        ctx.close()
+
+
+def test_job_api_rejects_bad_requests():
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = exactz.Context(0)
+    try:
+        f = torch.zeros((8, 9), dtype=torch.float32, device="cuda")
+        g = f.clone()
+        g[2, 3] = 0.5
+        with pytest.raises(exactz.ExactzError) as e:
+            ctx.job_create(f, g, 0.125)
+        assert e.value.status == exactz.E_BOUND
+        g[2, 3] = float("nan")
+        with pytest.raises(exactz.ExactzError) as e:
+            ctx.job_create(f, g, 0.125)
+        assert e.value.status == exactz.E_NONFINITE
+        job = ctx.job_create(f, f.clone(), 0.125)
+        ctx.step([job], 2)
+        done, r = job.poll()
+        assert done and r["status"] == exactz.OK and r["iterations"] == 0
+        job.release()
+    finally:
+        ctx.close()

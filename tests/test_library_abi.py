@@ -35,7 +35,7 @@ def test_binding_lists_match_header():
 def test_struct_layouts():
     from paper_2604_01397_amd import exactz
     assert ctypes.sizeof(exactz.Params) == 64
-    assert ctypes.sizeof(exactz.Result) == 96
+    assert ctypes.sizeof(exactz.Result) == 104
     assert ctypes.sizeof(exactz.Field) == 64 + 32
 
 

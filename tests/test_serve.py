@@ -1,0 +1,160 @@
+"""Serving loop (host logic) on a simulated executor and a virtual clock:
+admission by footprint, first-come-first-served order, continuous batching,
+rejection of oversized or failing jobs, latency and throughput bookkeeping."""
+import numpy as np
+import pytest
+
+from paper_2604_01397_amd.serve import JobSpec, Server
+
+
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+class SimExecutor:
+    """Each job needs `need` iterations; a step costs `per_step` seconds plus
+    `per_item` per active job; start costs `setup` seconds."""
+
+    def __init__(self, clock, per_step=1e-3, per_item=1e-4, setup=2e-3, fail_ids=()):
+        self.clock = clock
+        self.per_step, self.per_item, self.setup = per_step, per_item, setup
+        self.fail_ids = set(fail_ids)
+        self.used = 0
+        self.peak = 0
+        self.live = {}
+        self.log = []  # (event, job_id, time)
+
+    def footprint(self, spec):
+        return spec.meta["bytes"]
+
+    def start(self, spec):
+        if spec.job_id in self.fail_ids:
+            raise ValueError("bad input")
+        self.clock.t += self.setup
+        h = {"id": spec.job_id, "need": spec.meta["need"], "done": 0, "bytes": spec.meta["bytes"]}
+        self.used += h["bytes"]
+        self.peak = max(self.peak, self.used)
+        self.live[spec.job_id] = h
+        self.log.append(("start", spec.job_id, self.clock.t))
+        return h
+
+    def step(self, handles, iters):
+        assert handles
+        self.clock.t += self.per_step + self.per_item * len(handles)
+        for h in handles:
+            h["done"] = min(h["need"], h["done"] + iters)
+
+    def poll(self, h):
+        done = h["done"] >= h["need"]
+        return done, {"iterations": h["done"], "job": h["id"]}
+
+    def finish(self, h):
+        self.used -= h["bytes"]
+        del self.live[h["id"]]
+        self.log.append(("finish", h["id"], self.clock.t))
+        return ("out", h["id"])
+
+
+def _trace(n, rate, seed, big=None):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    specs = []
+    for j in range(n):
+        b = int(rng.integers(1, 8)) * 100
+        if big is not None and j in big:
+            b = big[j]
+        specs.append(JobSpec(j, float(t[j]), (4, 4, 4), 256,
+                             meta={"bytes": b, "need": int(rng.integers(1, 12))}))
+    return specs
+
+
+def test_all_jobs_complete_within_budget():
+    clk = VirtualClock()
+    ex = SimExecutor(clk)
+    srv = Server(ex, budget_bytes=1500, max_active=8, iters_per_step=2, clock=clk, sleep=clk.sleep,
+                 keep_outputs=True)
+    rep = srv.run(_trace(60, rate=400.0, seed=1))
+    s = rep.summary()
+    assert s["completed"] == 60 and s["rejected"] == 0
+    assert ex.peak <= 1500 and rep.max_bytes <= 1500
+    assert rep.max_active <= 8
+    assert not ex.live
+    for r in rep.records:
+        assert r.latency > 0 and r.admitted >= r.spec.arrival - 1e-12
+        assert r.completed >= r.admitted
+        assert r.outputs == ("out", r.spec.job_id)
+        # a job needs ceil(need / 2) steps of 2 iterations
+        assert r.result["iterations"] == r.spec.meta["need"]
+    assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
+    assert s["throughput_GBps"] > 0
+
+
+def test_first_come_first_served_admission():
+    clk = VirtualClock()
+    ex = SimExecutor(clk)
+    srv = Server(ex, budget_bytes=900, max_active=4, clock=clk, sleep=clk.sleep)
+    rep = srv.run(_trace(40, rate=1000.0, seed=2))
+    starts = [j for ev, j, _ in ex.log if ev == "start"]
+    assert starts == sorted(starts)  # arrivals are in id order
+    adm = [r.admitted for r in rep.records]
+    assert adm == sorted(adm)
+
+
+def test_continuous_batching_admits_while_others_run():
+    clk = VirtualClock()
+    ex = SimExecutor(clk)
+    srv = Server(ex, budget_bytes=10_000, max_active=16, clock=clk, sleep=clk.sleep)
+    specs = _trace(30, rate=2000.0, seed=3)
+    rep = srv.run(specs)
+    # some job started while an earlier one was still active
+    live, overlap = set(), False
+    for ev, j, _ in ex.log:
+        if ev == "start":
+            overlap |= bool(live)
+            live.add(j)
+        else:
+            live.discard(j)
+    assert overlap
+    # and a late job finished before an early long one
+    fin = [j for ev, j, _ in ex.log if ev == "finish"]
+    assert fin != sorted(fin)
+    assert rep.summary()["completed"] == 30
+
+
+def test_oversized_and_failing_jobs_are_reported_not_fatal():
+    clk = VirtualClock()
+    ex = SimExecutor(clk, fail_ids={5})
+    srv = Server(ex, budget_bytes=1000, max_active=4, clock=clk, sleep=clk.sleep)
+    rep = srv.run(_trace(12, rate=100.0, seed=4, big={3: 5000}))
+    errs = {r.spec.job_id: r.error for r in rep.records if r.error}
+    assert set(errs) == {3, 5}
+    assert "budget" in errs[3] and "bad input" in errs[5]
+    s = rep.summary()
+    assert s["completed"] == 10 and s["rejected"] == 2
+    assert not ex.live
+
+
+def test_idle_server_waits_for_arrivals():
+    clk = VirtualClock()
+    ex = SimExecutor(clk)
+    specs = [JobSpec(0, 5.0, (2, 2), 16, meta={"bytes": 10, "need": 1}),
+             JobSpec(1, 9.0, (2, 2), 16, meta={"bytes": 10, "need": 3})]
+    rep = Server(ex, 100, clock=clk, sleep=clk.sleep).run(specs)
+    a, b = rep.records
+    assert a.admitted >= 5.0 and b.admitted >= 9.0
+    assert a.latency < 1.0 and b.latency < 1.0
+
+
+def test_bad_configuration_rejected():
+    clk = VirtualClock()
+    with pytest.raises(ValueError):
+        Server(SimExecutor(clk), budget_bytes=0)
+    with pytest.raises(ValueError):
+        Server(SimExecutor(clk), budget_bytes=10, iters_per_step=0)
