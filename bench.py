@@ -59,7 +59,8 @@ def main():
     ap.add_argument("--edge", type=int, default=512, help="field edge (default 512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--poll", type=int, default=0)
-    ap.add_argument("--tile", type=int, default=404, help="box shape tile_y*100+tile_z")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="box shape tile_y*100+tile_z (0: by dimensionality, 8 x 4 here)")
     ap.add_argument("--sweep", action="store_true", help="time every compiled box shape first")
     ap.add_argument("--grid", type=int, default=-1, help="stencil grid (-1 persistent, 0 per box)")
     ap.add_argument("--frontier", type=int, default=1, help="1: frontier check passes (default)")

@@ -92,6 +92,21 @@ struct Busy {
 
 namespace exz {
 
+// Box shape when none is set: 64 x 8 x 4 for volumes, 64 x 16 rows for
+// planes, single rows for lines (taller boxes would leave threads idle).
+void default_box(int ny, int nz, int &ty, int &tz) {
+  if (nz > 1) {
+    ty = 8;
+    tz = 4;
+  } else if (ny > 1) {
+    ty = 16;
+    tz = 1;
+  } else {
+    ty = 1;
+    tz = 1;
+  }
+}
+
 // Validates params and fills geometry, bounds and step of fd.
 exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd) {
   std::memset(&fd, 0, sizeof fd);
@@ -122,11 +137,14 @@ exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd) {
   fd.N = p->n_steps;
   fd.mode = p->event_mode;
   fd.resume = p->resume ? 1 : 0;
-  const int ty = ctx ? ctx->tile_y : 4;
+  int ty = ctx ? ctx->tile_y : 0, tz = ctx ? ctx->tile_z : 0;
+  if (ty == 0) default_box(fd.ny, fd.nz, ty, tz);
   fd.tile_y = ty;
+  fd.tile_z = tz;
+  fd.ty_shift = __builtin_ctz((unsigned)ty);  // compiled box sides are powers of two
+  fd.tz_shift = __builtin_ctz((unsigned)tz);
   fd.tiles_x = (fd.nx + 63) / 64;
   fd.tiles_y = (fd.ny + ty - 1) / ty;
-  fd.tile_z = ctx ? ctx->tile_z : 4;
   fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
   const int64_t ntiles = (int64_t)fd.tiles_x * fd.tiles_y * fd.tiles_z;
   if (ntiles >= (1ll << 31)) return fail(ctx, EXZ_E_INVALID, "too many tiles");
@@ -164,7 +182,7 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
   off[1] = L.add(3 * n);                                     // code, low
   off[2] = L.add(8 * (size_t)fd.nchunk);                     // cpbits
   off[3] = L.add(4 * ((size_t)fd.nchunk + 1));               // cpoff
-  off[4] = L.add(8 * (size_t)fd.nchunk);                     // target bitmask
+  off[4] = L.add(n);                                         // target marks
   off[5] = L.add(4 * n);                                     // rank_of
   off[6] = own_cnt ? L.add(n) : 0;                           // cnt
   off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
@@ -212,7 +230,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   fd.code = (uint8_t *)(base + oa[1] + 2 * (size_t)fd.n);
   fd.cpbits = (unsigned long long *)(base + oa[2]);
   fd.cpoff = (uint32_t *)(base + oa[3]);
-  fd.tbits = (uint32_t *)(base + oa[4]);
+  fd.tmark = (uint8_t *)(base + oa[4]);
   fd.bdirty = (uint8_t *)(base + oa[8]);
   fd.rank_of = (uint32_t *)(base + oa[5]);
   fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
@@ -378,21 +396,26 @@ exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value) {
   } else if (k == "graph") {
     ctx->graph = value != 0;
   } else if (k == "tile_z") {
-    if (!box_supported(ctx->tile_y, (int)value))
-      return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", ctx->tile_y, (int)value);
+    const int ty = ctx->tile_y ? ctx->tile_y : 4;
+    if (!box_supported(ty, (int)value))
+      return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", ty, (int)value);
+    ctx->tile_y = ty;
     ctx->tile_z = (int)value;
   } else if (k == "tile_y") {
-    if (!box_supported((int)value, ctx->tile_z))
-      return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", (int)value, ctx->tile_z);
+    const int tz = ctx->tile_z ? ctx->tile_z : 1;
+    if (!box_supported((int)value, tz))
+      return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", (int)value, tz);
     ctx->tile_y = (int)value;
+    ctx->tile_z = tz;
   } else if (k == "frontier") {  // 1: re-check only changed boxes (reformulated mode)
     ctx->frontier = value != 0;
   } else if (k == "grid") {  // stencil work-groups: -1 persistent (default), 0 one per box
     if (value < -1 || value > (1 << 24)) return fail(ctx, EXZ_E_INVALID, "grid must be -1..2^24");
     ctx->grid_blocks = (int)value;
-  } else if (k == "tile") {  // tile_y * 100 + tile_z, set together
+  } else if (k == "tile") {  // tile_y * 100 + tile_z, set together; 0 = by dimensionality
     const int ty = (int)(value / 100), tz = (int)(value % 100);
-    if (!box_supported(ty, tz)) return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", ty, tz);
+    if (value != 0 && !box_supported(ty, tz))
+      return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", ty, tz);
     ctx->tile_y = ty;
     ctx->tile_z = tz;
   } else {

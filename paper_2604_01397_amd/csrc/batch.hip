@@ -44,7 +44,10 @@ __device__ __forceinline__ uint32_t find_field(const uint32_t *base, uint32_t nf
 template <int TY, int TZ>
 __global__ void __launch_bounds__(64 * TY)
     k_check_batch(const FieldDev *fields, const uint32_t *lists, const uint32_t *conn) {
-  __shared__ double S[Box<TY, TZ>::NE];  // sized for float64; float32 uses the front
+  __shared__ union {
+    CheckLds<float, TY, TZ> f;
+    CheckLds<double, TY, TZ> d;
+  } L;
   const uint32_t nf = lists[0], total = lists[1];
   const uint32_t *field = lists + 2, *base = lists + 2 + nf;
   for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
@@ -52,19 +55,17 @@ __global__ void __launch_bounds__(64 * TY)
     const FieldDev &fd = fields[field[k]];
     if (!fd.st->done) {
       const BoxOrigin o = box_of(fd, it - base[k], TY, TZ);
-      StageMap<TY, TZ> m;  // per field: its strides differ
-      stage_map<TY, TZ>(fd, threadIdx.y * 64 + threadIdx.x, m);
       if (fd.dtype == 0)
-        check_box<float, TY, TZ>(fd, conn, o, (float *)S, m);
+        check_box<float, TY, TZ>(fd, conn, o, L.f);
       else
-        check_box<double, TY, TZ>(fd, conn, o, S, m);
+        check_box<double, TY, TZ>(fd, conn, o, L.d);
     }
     __syncthreads();
   }
 }
 
-// ApplyBoundedEdits: field k owns items [base[k], base[k+1]), one per 256
-// words of its target set.
+// ApplyBoundedEdits: field k owns items [base[k], base[k+1]), one per
+// APPLY_CHUNK vertices.
 __global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *fields,
                                                              const uint32_t *lists) {
   const uint32_t nf = lists[0], total = lists[1];
@@ -74,13 +75,11 @@ __global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *fie
     const FieldDev &fd = fields[field[k]];
     if (!fd.st->done) {
       EditCount ec = {{0, 0, 0, 0, 0}};
-      const uint32_t w = (it - base[k]) * APPLY_BLOCK + threadIdx.x;
-      if (w < (uint32_t)(2 * fd.nchunk)) {
-        if (fd.dtype == 0)
-          apply_word<float>(fd, w, ec);
-        else
-          apply_word<double>(fd, w, ec);
-      }
+      const uint32_t v = (it - base[k]) * APPLY_CHUNK;
+      if (fd.dtype == 0)
+        apply_chunk<float>(fd, v, ec);
+      else
+        apply_chunk<double>(fd, v, ec);
       flush_counts<APPLY_BLOCK / 64>(fd.st, ec, it);
     }
     __syncthreads();
@@ -158,7 +157,7 @@ namespace exz {
 
 // Launch geometry shared by all members of a batch.
 struct BatchShape {
-  int ty3 = 4, tz3 = 4;  // boxes for 3D fields
+  int ty3 = 8, tz3 = 4;  // boxes for 3D fields
   int ty2 = 16, tz2 = 1; // boxes for 1D/2D fields
 };
 
@@ -218,9 +217,9 @@ static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dli
   }
 }
 
-// Items of the apply pass of one field: 256 target words each.
+// Items of the apply pass of one field: APPLY_CHUNK vertices each.
 static uint32_t apply_items(const FieldDev &fd) {
-  return (uint32_t)((2 * fd.nchunk + APPLY_BLOCK - 1) / APPLY_BLOCK);
+  return (uint32_t)(((uint32_t)fd.n + APPLY_CHUNK - 1) / APPLY_CHUNK);
 }
 
 exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *dev_fields,
@@ -363,8 +362,10 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
   std::vector<Member> mem;
   std::vector<int> singles;  // fields run through the single-field driver
   BatchShape shape;
-  shape.ty3 = ctx->tile_y;
-  shape.tz3 = ctx->tile_z;
+  if (ctx->tile_y) {  // an explicit box shape applies to the 3D members
+    shape.ty3 = ctx->tile_y;
+    shape.tz3 = ctx->tile_z;
+  }
   for (int k = 0; k < nfields; ++k) {
     const exz_field &fl = fields[k];
     Member m;
@@ -387,6 +388,8 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     const bool three = m.fd.nz > 1;
     m.fd.tile_y = three ? shape.ty3 : shape.ty2;
     m.fd.tile_z = three ? shape.tz3 : shape.tz2;
+    m.fd.ty_shift = __builtin_ctz((unsigned)m.fd.tile_y);
+    m.fd.tz_shift = __builtin_ctz((unsigned)m.fd.tile_z);
     m.fd.tiles_y = (m.fd.ny + m.fd.tile_y - 1) / m.fd.tile_y;
     m.fd.tiles_z = (m.fd.nz + m.fd.tile_z - 1) / m.fd.tile_z;
     m.fd.ntiles = m.fd.tiles_x * m.fd.tiles_y * m.fd.tiles_z;
@@ -431,7 +434,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.code = (uint8_t *)(b + oa[k][1] + 2 * (size_t)fd.n);
       fd.cpbits = (unsigned long long *)(b + oa[k][2]);
       fd.cpoff = (uint32_t *)(b + oa[k][3]);
-      fd.tbits = (uint32_t *)(b + oa[k][4]);
+      fd.tmark = (uint8_t *)(b + oa[k][4]);
       fd.bdirty = (uint8_t *)(b + oa[k][8]);
       fd.rank_of = (uint32_t *)(b + oa[k][5]);
       uint8_t *cnt_io = fields[mem[k].index].cnt_io;
@@ -592,8 +595,11 @@ exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, ex
   if (st == EXZ_OK) {
     FieldDev &fd = job->fd;
     const bool three = fd.nz > 1;  // same boxes as the batched launches
-    fd.tile_y = three ? 4 : 16;
-    fd.tile_z = three ? 4 : 1;
+    const BatchShape shape;
+    fd.tile_y = three ? shape.ty3 : shape.ty2;
+    fd.tile_z = three ? shape.tz3 : shape.tz2;
+    fd.ty_shift = __builtin_ctz((unsigned)fd.tile_y);
+    fd.tz_shift = __builtin_ctz((unsigned)fd.tile_z);
     fd.tiles_y = (fd.ny + fd.tile_y - 1) / fd.tile_y;
     fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
     fd.ntiles = fd.tiles_x * fd.tiles_y * fd.tiles_z;

@@ -49,8 +49,8 @@ struct exz_ctx {
   bool profile = false;
   bool graph = true;
   int poll = 0;     // 0 = adaptive
-  int tile_y = 4;
-  int tile_z = 4;
+  int tile_y = 0;  // 0: box shape chosen by the field's dimensionality
+  int tile_z = 0;
   int grid_blocks = -1;
   bool frontier = true;
   std::string last_error;

@@ -75,6 +75,7 @@ struct FieldDev {
   int32_t grid_blocks;       // stencil grid: 0 one block per box, < 0 persistent default, > 0 fixed
   int32_t trace_cap;
   int32_t frontier;     // 1: re-check only boxes whose closed neighbourhood changed
+  int32_t ty_shift, tz_shift;  // log2 of tile_y / tile_z
   int32_t dlt[16];      // linear index offset of each slot (dlt[SELF] = 0)
   double xiT, delta;    // in the field type, widened exactly to double
   const void *f;
@@ -93,7 +94,7 @@ struct FieldDev {
   uint32_t *sel_f;      // 2 per saddle: selections in f (join, split) or ~0
   uint32_t *lab;        // 2n: g's descent / ascent labels (original mode)
   uint32_t *lab_f;      // 2n: f's resolved path termini (original mode, certificate)
-  uint32_t *tbits;      // 2 * nchunk words: the target set of the iteration, one bit per vertex
+  uint8_t *tmark;       // n: the target set of the iteration (1 = decrease this vertex)
   uint8_t *bdirty;      // ntiles: boxes whose closed neighbourhood the last apply changed
   int64_t *trace;       // 2 * trace_cap (|S|, changed) per iteration, nullable
   State *st;
@@ -102,11 +103,10 @@ struct FieldDev {
 // ---------------------------------------------------------------------------
 // device helpers
 
-// Adds vertex t to the target set (one bit per vertex; several checks may
-// name the same target, the set keeps it once).
-__device__ __forceinline__ void mark_target(uint32_t *bits, uint32_t t) {
-  atomicOr(bits + (t >> 5), 1u << (t & 31u));
-}
+// Adds vertex t to the target set: a plain byte store (every writer stores
+// the same value, so concurrent marks of one target need no atomics; the
+// cache keeps per-byte dirty masks, so neighbouring marks do not clash).
+__device__ __forceinline__ void mark_target(uint8_t *marks, uint32_t t) { marks[t] = 1; }
 
 // Simulation of Simplicity: (a, ia) < (b, ib).  Bitwise, not short-circuit,
 // so that the compiler emits straight-line compares instead of branches.

@@ -24,6 +24,8 @@
 // thread (the kernels are bound by HBM latency x parallelism otherwise), and
 // each thread evaluates TZ vertices of one (x, y) column from LDS.  Halo
 // re-reads are served by L2: consecutive boxes run on the same XCD.
+#include <algorithm>
+
 #include "loop_box.h"
 
 namespace exz {
@@ -54,17 +56,15 @@ template <class T, int TY, int TZ>
 __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *__restrict__ conn) {
   State *st = fd.st;
   if (st->done) return;
-  __shared__ T S[Box<TY, TZ>::NE];
+  __shared__ CheckLds<T, TY, TZ> L;
   __shared__ unsigned long long pick;
-  StageMap<TY, TZ> m;
-  stage_map<TY, TZ>(fd, threadIdx.y * 64 + threadIdx.x, m);
   const BoxWalk w = box_walk(fd);
   const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
   uint32_t done_v = 0;  // vertices checked by this work-group (lead thread)
   if (!fd.frontier || st->dense) {
     for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
       const BoxOrigin o = box_of(fd, tile, TY, TZ);
-      check_box<T, TY, TZ>(fd, conn, o, S, m);
+      check_box<T, TY, TZ>(fd, conn, o, L);
       if (lead) done_v += box_vertices(fd, o, TY, TZ);
       __syncthreads();
     }
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
         const uint32_t k = (uint32_t)(__ffsll(b) - 1);
         b &= b - 1;
         const BoxOrigin o = box_of(fd, t0 + k * w.stride, TY, TZ);
-        check_box<T, TY, TZ>(fd, conn, o, S, m);
+        check_box<T, TY, TZ>(fd, conn, o, L);
         if (lead) done_v += box_vertices(fd, o, TY, TZ);
         __syncthreads();
       }
@@ -101,20 +101,23 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
 }
 
+// Critical-point order: every consecutive pair, one thread each.
+constexpr int CP_BLOCK = 256;
+
 template <class T>
-__global__ void __launch_bounds__(256) k_cpcmp(FieldDev fd) {
+__global__ void __launch_bounds__(CP_BLOCK) k_cpcmp(FieldDev fd) {
   if (fd.st->done) return;
-  const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t k = blockIdx.x * CP_BLOCK + threadIdx.x;
   if (k + 1 < (uint32_t)fd.K) cp_pair<T>(fd, k);
 }
 
-// ApplyBoundedEdits over the target bitmask, one thread per 32-vertex word.
+// ApplyBoundedEdits over the target marks, chunks of APPLY_CHUNK vertices.
 template <class T>
 __global__ void __launch_bounds__(APPLY_BLOCK) k_apply(FieldDev fd) {
   if (fd.st->done) return;
-  const uint32_t w = blockIdx.x * APPLY_BLOCK + threadIdx.x;
+  const uint32_t nchunks = ((uint32_t)fd.n + APPLY_CHUNK - 1) / APPLY_CHUNK;
   EditCount ec = {{0, 0, 0, 0, 0}};
-  if (w < (uint32_t)(2 * fd.nchunk)) apply_word<T>(fd, w, ec);
+  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) apply_chunk<T>(fd, c * APPLY_CHUNK, ec);
   flush_counts<APPLY_BLOCK / 64>(fd.st, ec, blockIdx.x);
 }
 
@@ -172,13 +175,14 @@ static void launch_check_cpcmp(const FieldDev &fd, const uint32_t *conn, const u
   if (fd.mode == 1)
     (void)launch_original_events(fd, comp, s);
   else if (fd.K > 1)
-    hipLaunchKernelGGL(k_cpcmp<T>, dim3((fd.K + 254) / 256), dim3(256), 0, s, fd);
+    hipLaunchKernelGGL(k_cpcmp<T>, dim3((fd.K - 1 + CP_BLOCK - 1) / CP_BLOCK), dim3(CP_BLOCK), 0, s,
+                       fd);
 }
 
 template <class T>
 static void launch_apply(const FieldDev &fd, hipStream_t s) {
-  const int grid = (2 * fd.nchunk + APPLY_BLOCK - 1) / APPLY_BLOCK;
-  hipLaunchKernelGGL(k_apply<T>, dim3(grid), dim3(APPLY_BLOCK), 0, s, fd);
+  const int chunks = (int)(((uint32_t)fd.n + APPLY_CHUNK - 1) / APPLY_CHUNK);
+  hipLaunchKernelGGL(k_apply<T>, dim3(std::min(chunks, 16384)), dim3(APPLY_BLOCK), 0, s, fd);
 }
 
 template <class T>
@@ -213,7 +217,7 @@ __global__ void k_targets_to_bytes(FieldDev fd, uint8_t *out) {
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   bool hit = false;
   if (t < (uint32_t)fd.n) {
-    hit = ((fd.tbits[t >> 5] >> (t & 31u)) & 1u) != 0;
+    hit = fd.tmark[t] != 0;
     out[t] = hit;
   }
   const uint32_t c = wave_sum((uint32_t)hit);

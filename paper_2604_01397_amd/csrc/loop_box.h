@@ -38,73 +38,64 @@ template <> __device__ __forceinline__ double outside_value<double>() {
   return __longlong_as_double(0x7FF8000000000000ll);
 }
 
-// Staging of a box plus its one-cell halo into LDS.  Each thread's element
-// offsets (relative to the halo's first cell) are the same for every box,
-// so they are computed once per kernel.  A box whose halo lies inside the
-// domain -- most of them -- loads with one add per element; a box at the
-// domain boundary clamps coordinates so every load stays valid and then
-// overwrites the cells outside the domain with outside_value().  Loads are
-// unconditional and their values always stored, so all of a thread's loads
-// are in flight at once (a value used on one path only invites the compiler
-// to move its load under that branch, one round trip per element).
-template <int TY, int TZ>
-struct StageMap {
-  using B = Box<TY, TZ>;
-  uint32_t off[B::R];  // element offset from the halo origin, in the field
-  uint32_t cell[B::R]; // (xx, yy, zz) of the element, packed 8:8:8
-};
-
-template <int TY, int TZ>
-__device__ __forceinline__ void stage_map(const FieldDev &fd, int tid, StageMap<TY, TZ> &m) {
-  using B = Box<TY, TZ>;
-#pragma unroll
-  for (int k = 0; k < B::R; ++k) {
-    const int e = min(tid + k * B::NT, B::NE - 1);
-    const int zz = e / B::PLANE, rem = e - zz * B::PLANE;
-    const int yy = rem / B::W, xx = rem - yy * B::W;
-    m.off[k] = (uint32_t)xx + (uint32_t)fd.nx * ((uint32_t)yy + (uint32_t)fd.ny * (uint32_t)zz);
-    m.cell[k] = (uint32_t)xx | ((uint32_t)yy << 8) | ((uint32_t)zz << 16);
-  }
-}
-
+// Staging of a box plus its one-cell halo into LDS, row by row: a row is
+// the 66 cells x0-1 .. x0+64 at one (y, z).  Wave w stages rows w, w + TY,
+// ... (cells x0-1 .. x0+62, one per lane, from a row address the whole wave
+// shares); the last two cells of every row come in one extra pass over all
+// rows.  Rows outside the domain, and cells left or right of it, are
+// staged as outside_value().  All loads of a thread are issued before the
+// first LDS write.
 template <int TY, int TZ, class V>
-__device__ __forceinline__ void stage_box(const FieldDev &fd, const V *src, V *S, BoxOrigin o,
-                                          int tid, const StageMap<TY, TZ> &m) {
+__device__ __forceinline__ void stage_rows(const FieldDev &fd, const V *__restrict__ src, V *S,
+                                           BoxOrigin o) {
   using B = Box<TY, TZ>;
-  V r[B::R];
-  const bool interior = o.x0 >= 1 && o.x0 + 64 <= fd.nx - 1 && o.y0 >= 1 &&
-                        o.y0 + TY <= fd.ny - 1 && o.z0 >= 1 && o.z0 + TZ <= fd.nz - 1;
-  uint32_t outside = 0;
-  if (interior) {
-    const V *base = src + ((uint32_t)(o.x0 - 1) +
-                           (uint32_t)fd.nx * ((uint32_t)(o.y0 - 1) + (uint32_t)fd.ny * (uint32_t)(o.z0 - 1)));
+  constexpr int NR = B::H * B::D;             // rows of the halo box
+  constexpr int RPW = (NR + TY - 1) / TY;     // rows per wave
+  constexpr int NEDGE = (2 * NR + 64 * TY - 1) / (64 * TY);  // edge cells per thread
+  // blocks are 64 wide, so threadIdx.y is the same on every lane of a wave
+  const int lane = threadIdx.x, w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int tid = w * 64 + lane;
+  const int nx = fd.nx, ny = fd.ny, nz = fd.nz;
+  const bool inner_x = o.x0 >= 1 && o.x0 + 64 <= nx - 1;
+  const int xl = o.x0 - 1 + lane;                      // this lane's cell of a row
+  const bool in_x = xl >= 0 && xl < nx;
+  const uint32_t cxl = (uint32_t)min(max(xl, 0), nx - 1);
+  V r[RPW];
 #pragma unroll
-    for (int k = 0; k < B::R; ++k) r[k] = base[m.off[k]];
-  } else {
-#pragma unroll
-    for (int k = 0; k < B::R; ++k) {
-      const int gx = o.x0 - 1 + (int)(m.cell[k] & 255u);
-      const int gy = o.y0 - 1 + (int)((m.cell[k] >> 8) & 255u);
-      const int gz = o.z0 - 1 + (int)(m.cell[k] >> 16);
-      const bool in = (gx >= 0) & (gx < fd.nx) & (gy >= 0) & (gy < fd.ny) & (gz >= 0) & (gz < fd.nz);
-      outside |= (uint32_t)!in << k;
-      const uint32_t cx = (uint32_t)min(max(gx, 0), fd.nx - 1);
-      const uint32_t cy = (uint32_t)min(max(gy, 0), fd.ny - 1);
-      const uint32_t cz = (uint32_t)min(max(gz, 0), fd.nz - 1);
-      r[k] = src[cx + (uint32_t)fd.nx * (cy + (uint32_t)fd.ny * cz)];
+  for (int k = 0; k < RPW; ++k) {
+    const int row = w + k * TY;
+    const int yy = row % B::H, zz = row / B::H;
+    const int gy = o.y0 - 1 + yy, gz = o.z0 - 1 + zz;
+    const bool row_in = row < NR && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+    r[k] = outside_value<V>();
+    if (row_in) {  // uniform across the wave
+      const V *rp = src + ((uint32_t)gz * (uint32_t)ny + (uint32_t)gy) * (uint32_t)nx;
+      const V v = rp[inner_x ? (uint32_t)xl : cxl];
+      r[k] = (inner_x || in_x) ? v : outside_value<V>();
     }
   }
+  V e[NEDGE];
 #pragma unroll
-  for (int k = 0; k < B::R; ++k) {
-    const int e = tid + k * B::NT;
-    if (e < B::NE) S[e] = r[k];
+  for (int k = 0; k < NEDGE; ++k) {
+    const int t = tid + k * 64 * TY;
+    const int row = t >> 1, side = t & 1;
+    const int yy = row % B::H, zz = row / B::H;
+    const int gy = o.y0 - 1 + yy, gz = o.z0 - 1 + zz, gx = o.x0 + 63 + side;
+    const bool in = t < 2 * NR && gy >= 0 && gy < ny && gz >= 0 && gz < nz && gx < nx;
+    const uint32_t cy = (uint32_t)min(max(gy, 0), ny - 1), cz = (uint32_t)min(max(gz, 0), nz - 1);
+    const uint32_t cx = (uint32_t)min(gx, nx - 1);
+    const V v = src[(cz * (uint32_t)ny + cy) * (uint32_t)nx + cx];
+    e[k] = in ? v : outside_value<V>();
   }
-  if (outside) {
 #pragma unroll
-    for (int k = 0; k < B::R; ++k) {
-      const int e = tid + k * B::NT;
-      if (e < B::NE && ((outside >> k) & 1u)) S[e] = outside_value<V>();
-    }
+  for (int k = 0; k < RPW; ++k) {
+    const int row = w + k * TY;
+    if (row < NR) S[row * B::W + lane] = r[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NEDGE; ++k) {
+    const int t = tid + k * 64 * TY;
+    if (t < 2 * NR) S[(t >> 1) * B::W + 64 + (t & 1)] = e[k];
   }
 }
 
@@ -122,32 +113,38 @@ __device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint3
   // (dz, dy, dx) on any grid where the slot is in the domain.
   constexpr int ORDER[NSLOT + 1] = {13, 11, 9, 7, 5, 3, 1, SELF, 0, 2, 4, 6, 8, 10, 12};
   const uint32_t vm = interior ? 0x3FFFu : slots_in_domain(x, y, z, fd.nx, fd.ny, fd.nz);
-  const T gi = P[0];
-  T gn[NSLOT];
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const int po = DZS[s] < 0 ? pm : DZS[s] > 0 ? pp : 0;
-    gn[s] = P[po + DYS[s] * HALO_W + DXS[s]];
-  }
-  // One pass in index order: with ">=" a later (higher-index) candidate wins
-  // a tie, which is the SoS maximum; with "<" the earlier (lower-index) one
-  // keeps it, which is the SoS minimum.  A neighbour with a lower index is
-  // below i when its value is <= g_i, one with a higher index when it is
-  // < g_i.  NaN (outside the domain) never compares true.
-  T bmax = -INFINITY, bmin = INFINITY;
-  int asc = SELF, desc = SELF;
-  uint32_t lower = 0;
+  T v[NSLOT + 1];  // closed neighbourhood in index order
 #pragma unroll
   for (int q = 0; q <= NSLOT; ++q) {
     const int s = ORDER[q];
-    const T v = s == SELF ? gi : gn[s];
-    if (s != SELF) lower |= (uint32_t)(q < 7 ? v <= gi : v < gi) << s;
-    const bool up = v >= bmax;
-    bmax = up ? v : bmax;
-    asc = up ? s : asc;
-    const bool dn = v < bmin;
-    bmin = dn ? v : bmin;
-    desc = dn ? s : desc;
+    const int po = s == SELF ? 0 : DZS[s] < 0 ? pm : DZS[s] > 0 ? pp : 0;
+    v[q] = s == SELF ? P[0] : P[po + DYS[s] * HALO_W + DXS[s]];
+  }
+  const T gi = v[7];
+  // Extreme values first (NaN, outside the domain, is ignored by fmax /
+  // fmin), then the slot: the SoS maximum is the highest-index vertex
+  // holding the largest value, the SoS minimum the lowest-index vertex
+  // holding the smallest.
+  T hi = gi, lo = gi;
+#pragma unroll
+  for (int q = 0; q <= NSLOT; ++q) {
+    if (q == 7) continue;
+    hi = fmax(hi, v[q]);
+    lo = fmin(lo, v[q]);
+  }
+  int asc = SELF, desc = SELF;
+#pragma unroll
+  for (int q = 0; q <= NSLOT; ++q) {
+    asc = v[q] == hi ? ORDER[q] : asc;
+    desc = v[NSLOT - q] == lo ? ORDER[NSLOT - q] : desc;
+  }
+  // A neighbour with a lower index is below i when its value is <= g_i,
+  // one with a higher index when it is < g_i; NaN never compares true.
+  uint32_t lower = 0;
+#pragma unroll
+  for (int q = 0; q <= NSLOT; ++q) {
+    if (q == 7) continue;
+    lower |= (uint32_t)(q < 7 ? v[q] <= gi : v[q] < gi) << ORDER[q];
   }
   if (fd.mode == 1) {  // vertex indices are needed for path tracing only
     asc_v = (uint32_t)((int)i + fd.dlt[asc]);
@@ -180,57 +177,68 @@ __device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint3
   return req;
 }
 
-// Adds the targets named by vertex i's request mask r (bit s: the neighbour
-// in slot s, bit SELF: i itself).
-__device__ __forceinline__ void post_targets(const FieldDev &fd, uint32_t i, uint32_t r) {
-  if ((r >> SELF) & 1u) mark_target(fd.tbits, i);
-  r &= LOW_MASK;
-  while (r) {
-    const int s = __ffs(r) - 1;
-    r &= r - 1;
-    mark_target(fd.tbits, (uint32_t)((int)i + fd.dlt[s]));
-  }
-}
-
 // Vertices of the box inside the domain.
 __device__ __forceinline__ uint32_t box_vertices(const FieldDev &fd, BoxOrigin o, int TY, int TZ) {
   return (uint32_t)(min(64, fd.nx - o.x0) * min(TY, fd.ny - o.y0) * min(TZ, fd.nz - o.z0));
 }
 
-// CheckConstraints on one box: stage g, add the targets every vertex names
-// to the target set (and, in original mode, write g's descent / ascent
-// pointers).
+// Adds the targets named by vertex i's request mask r (bit s: the neighbour
+// in slot s, bit SELF: i itself).
+__device__ __forceinline__ void post_targets(const FieldDev &fd, uint32_t i, uint32_t r) {
+  if ((r >> SELF) & 1u) mark_target(fd.tmark, i);
+  r &= LOW_MASK;
+  while (r) {
+    const int s = __ffs(r) - 1;
+    r &= r - 1;
+    mark_target(fd.tmark, (uint32_t)((int)i + fd.dlt[s]));
+  }
+}
+
+// LDS of one check work-group: the staged box and the reference codes of
+// its own vertices (code byte | lower mask << 8).
+template <class T, int TY, int TZ>
+struct CheckLds {
+  T S[Box<TY, TZ>::NE];
+  uint32_t ref[TZ][64 * TY];
+};
+
+// CheckConstraints on one box: stage g (and the box's reference codes), add
+// the targets every vertex names to the target set (and, in original mode,
+// write g's descent / ascent pointers).  The caller synchronises the block
+// after it.
 template <class T, int TY, int TZ>
 __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__restrict__ conn,
-                                          BoxOrigin o, T *S, const StageMap<TY, TZ> &m) {
+                                          BoxOrigin o, CheckLds<T, TY, TZ> &L) {
   using B = Box<TY, TZ>;
   const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx;
   const int x = o.x0 + lx, y = o.y0 + ly;
   const bool col = x < fd.nx && y < fd.ny;
   const uint32_t plane = (uint32_t)fd.nx * (uint32_t)fd.ny;
   const uint32_t i0 = (uint32_t)x + (uint32_t)fd.nx * ((uint32_t)y + (uint32_t)fd.ny * (uint32_t)o.z0);
-  uint32_t codes[TZ], lows[TZ];
+  uint32_t refs[TZ];
 #pragma unroll
   for (int k = 0; k < TZ; ++k) {  // issued with the staging loads, unconditionally
     const bool in = col && o.z0 + k < fd.nz;
     const uint32_t idx = in ? i0 + k * plane : 0u;
     const uint32_t cb = fd.code[idx], lb = fd.low[idx];
-    codes[k] = in ? cb : 0u;
-    lows[k] = in ? lb : 0u;
+    refs[k] = cb | (lb << 8);
   }
-  stage_box<TY, TZ>(fd, (const T *)fd.g, S, o, tid, m);
+  stage_rows<TY, TZ>(fd, (const T *)fd.g, L.S, o);
+#pragma unroll
+  for (int k = 0; k < TZ; ++k) L.ref[k][tid] = refs[k];
   const bool interior = o.x0 >= 1 && o.x0 + 64 <= fd.nx - 1 && o.y0 >= 1 &&
                         o.y0 + TY <= fd.ny - 1 && o.z0 >= 1 && o.z0 + TZ <= fd.nz - 1;
   __syncthreads();
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < TZ; ++k) {
     const int z = o.z0 + k;
     if (col && z < fd.nz) {
       const uint32_t i = i0 + k * plane;
-      const T *c = S + (k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1;
+      const T *c = L.S + (k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1;
+      const uint32_t rf = L.ref[k][tid];
       uint32_t av = 0, dv = 0;
-      const uint32_t r = check_vertex<T>(fd, conn, c, -B::PLANE, B::PLANE, x, y, z, i, codes[k],
-                                         lows[k], av, dv, interior);
+      const uint32_t r = check_vertex<T>(fd, conn, c, -B::PLANE, B::PLANE, x, y, z, i, rf & 255u,
+                                         rf >> 8, av, dv, interior);
       if (r) post_targets(fd, i, r);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
         fd.lab[i] = dv;
@@ -249,7 +257,7 @@ __device__ __forceinline__ void cp_pair(const FieldDev &fd, uint32_t r) {
   const T a = V[r], b = V[r + 1];
   if (b > a) return;
   const uint32_t ia = fd.cp_idx[r], ib = fd.cp_idx[r + 1];
-  if (sos_lt(b, ib, a, ia)) mark_target(fd.tbits, ia);
+  if (sos_lt(b, ib, a, ia)) mark_target(fd.tmark, ia);
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -266,61 +274,114 @@ struct EditCount {
   uint32_t v[5];  // targets, changed, lossless, floored, first edits
 };
 
-// Marks every box whose check reads vertex t (the box plus its one-cell
-// halo contains t), so the next frontier check visits it.
-__device__ __forceinline__ void mark_boxes(const FieldDev &fd, uint32_t t) {
-  const uint32_t x = t % (uint32_t)fd.nx, r = t / (uint32_t)fd.nx;
-  const uint32_t y = r % (uint32_t)fd.ny, z = r / (uint32_t)fd.ny;
-  const uint32_t ty = (uint32_t)fd.tile_y, tz = (uint32_t)fd.tile_z;
-  const uint32_t bx0 = x ? (x - 1) >> 6 : 0, bx1 = min((x + 1) >> 6, (uint32_t)fd.tiles_x - 1);
-  const uint32_t by0 = y ? (y - 1) / ty : 0, by1 = min((y + 1) / ty, (uint32_t)fd.tiles_y - 1);
-  const uint32_t bz0 = z ? (z - 1) / tz : 0, bz1 = min((z + 1) / tz, (uint32_t)fd.tiles_z - 1);
+// Marks every box whose check reads a vertex of the row segment
+// x0 .. x1 at (y, z): the boxes whose cells plus one-cell halo contain it,
+// so the next frontier check visits them.
+__device__ __forceinline__ void mark_box_range(const FieldDev &fd, uint32_t x0, uint32_t x1,
+                                               uint32_t y, uint32_t z) {
+  const uint32_t bx0 = x0 ? (x0 - 1) >> 6 : 0, bx1 = min((x1 + 1) >> 6, (uint32_t)fd.tiles_x - 1);
+  const uint32_t by0 = y ? (y - 1) >> fd.ty_shift : 0;
+  const uint32_t by1 = min((y + 1) >> fd.ty_shift, (uint32_t)fd.tiles_y - 1);
+  const uint32_t bz0 = z ? (z - 1) >> fd.tz_shift : 0;
+  const uint32_t bz1 = min((z + 1) >> fd.tz_shift, (uint32_t)fd.tiles_z - 1);
   for (uint32_t bz = bz0; bz <= bz1; ++bz)
     for (uint32_t by = by0; by <= by1; ++by)
       for (uint32_t bx = bx0; bx <= bx1; ++bx)
         fd.bdirty[bx + (uint32_t)fd.tiles_x * (by + (uint32_t)fd.tiles_y * bz)] = 1;
 }
 
-// ApplyBoundedEdits on the 32 vertices of target word w; clears the word
-// and adds this thread's counts to ec.  In frontier mode every vertex whose
-// value or count moved marks the boxes that read it.
-template <class T>
-__device__ __forceinline__ void apply_word(const FieldDev &fd, uint32_t w, EditCount &ec) {
-  uint32_t bits = fd.tbits[w];
-  if (!bits) return;
-  fd.tbits[w] = 0;
-  ec.v[0] += (uint32_t)__popc(bits);
-  T *G = (T *)fd.g;
-  const T *F = (const T *)fd.f;
-  const T xiT = (T)fd.xiT, delta = (T)fd.delta;
-  while (bits) {
-    const uint32_t t = w * 32u + (uint32_t)(__ffs(bits) - 1);
-    bits &= bits - 1;
-    const T g0 = G[t], fv = F[t];
-    const uint32_t c0 = fd.cnt[t], rk = fd.rank_of[t];
-    const T L = lower_bound(fv, xiT);
-    if (g0 == L) continue;  // at the floor: blocked
-    const uint32_t c = c0 + 1;
-    fd.cnt[t] = (uint8_t)c;
-    T v;
-    if (c > (uint32_t)fd.N) {
-      v = L;  // (N+1)-th edit: store the lower bound itself
-      ++ec.v[2];
-    } else {
-      const T cand = g0 - delta;
-      v = cand < L ? L : cand;
-    }
-    G[t] = v;
-    if (rk != 0xFFFFFFFFu) ((T *)fd.cp_val)[rk] = v;
-    ++ec.v[1];
-    ec.v[3] += v == L;
-    ec.v[4] += c == 1;
-    if (fd.frontier) mark_boxes(fd, t);
+// Box marks for the vertices of a 64-vertex run (run_base + lane) set in
+// the wave-uniform mask `moved`: one range when they lie on one grid row
+// (marked by lane 0), else each moving lane marks its own vertex.
+__device__ __forceinline__ void mark_run_boxes(const FieldDev &fd, uint32_t run_base,
+                                               unsigned long long moved, bool mine) {
+  const uint32_t nx = (uint32_t)fd.nx, ny = (uint32_t)fd.ny;
+  const uint32_t lo = run_base + (uint32_t)(__ffsll(moved) - 1);
+  const uint32_t hi = run_base + 63u - (uint32_t)__clzll(moved);
+  const uint32_t x = lo % nx, r = lo / nx;
+  if (x + (hi - lo) < nx) {
+    if (__lane_id() == 0) mark_box_range(fd, x, x + (hi - lo), r % ny, r / ny);
+    return;
+  }
+  if (mine) {
+    const uint32_t t = run_base + __lane_id();
+    const uint32_t tx = t % nx, tr = t / nx;
+    mark_box_range(fd, tx, tx, tr % ny, tr / ny);
   }
 }
 
-// Work-group size of the apply passes (threads, one target word each).
+// Work-group size of the apply passes and the vertices one work-group
+// covers per chunk: each wave takes 256 consecutive vertices as four runs
+// of 64 (one vertex per lane, so every load and store is coalesced).
 constexpr int APPLY_BLOCK = 256;
+constexpr uint32_t APPLY_CHUNK = 1024;
+
+// ApplyBoundedEdits on the chunk starting at vertex `base`; clears the
+// marks it consumes and adds this thread's counts to ec.  A wave without a
+// marked vertex stops after reading its marks; otherwise the loads of all
+// its targets go out together.  In frontier mode the vertices whose value
+// or count moved mark the boxes that read them.
+template <class T>
+__device__ __forceinline__ void apply_chunk(const FieldDev &fd, uint32_t base, EditCount &ec) {
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t v0 = base + w * 256u + lane, n = (uint32_t)fd.n;
+  uint32_t mk[4];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint32_t v = v0 + 64u * c;
+    mk[c] = v < n ? fd.tmark[v] : 0u;
+    any |= mk[c] != 0;
+  }
+  if (!__any(any)) return;
+  T *G = (T *)fd.g;
+  const T *F = (const T *)fd.f;
+  const T xiT = (T)fd.xiT, delta = (T)fd.delta;
+  T g0[4], fv[4];
+  uint32_t c0[4], rk[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {  // unmarked lanes read vertex 0, always valid
+    const uint32_t t = mk[c] ? v0 + 64u * c : 0u;
+    g0[c] = G[t];
+    fv[c] = F[t];
+    c0[c] = fd.cnt[t];
+    rk[c] = fd.rank_of[t];
+  }
+  bool moved[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    moved[c] = false;
+    if (!mk[c]) continue;
+    const uint32_t t = v0 + 64u * c;
+    fd.tmark[t] = 0;
+    ++ec.v[0];
+    const T L = lower_bound(fv[c], xiT);
+    if (g0[c] == L) continue;  // at the floor: blocked
+    const uint32_t cn = c0[c] + 1;
+    fd.cnt[t] = (uint8_t)cn;
+    T v;
+    if (cn > (uint32_t)fd.N) {
+      v = L;  // (N+1)-th edit: store the lower bound itself
+      ++ec.v[2];
+    } else {
+      const T cand = g0[c] - delta;
+      v = cand < L ? L : cand;
+    }
+    G[t] = v;
+    if (rk[c] != 0xFFFFFFFFu) ((T *)fd.cp_val)[rk[c]] = v;
+    moved[c] = true;
+    ++ec.v[1];
+    ec.v[3] += v == L;
+    ec.v[4] += cn == 1;
+  }
+  if (fd.frontier) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const unsigned long long b = __ballot(moved[c]);
+      if (b) mark_run_boxes(fd, v0 - lane + 64u * c, b, moved[c]);
+    }
+  }
+}
 
 // Block reduction of the edit counts, added to one of the field's 64 shards.
 template <int TY>

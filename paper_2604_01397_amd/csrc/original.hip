@@ -148,7 +148,7 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   // C2: saddle order
   if (k + 1 < ns) {
     const uint32_t rn = fd.sad_rank[k + 1];
-    if (sos_lt(V[rn], fd.cp_idx[rn], V[rk], s)) mark_target(fd.tbits, s);
+    if (sos_lt(V[rn], fd.cp_idx[rn], V[rk], s)) mark_target(fd.tmark, s);
   }
   // C3: selected extrema along the integral paths of g
   const uint32_t mf = fd.sel_f[2 * k], Mf = fd.sel_f[2 * k + 1];
@@ -165,12 +165,12 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   }
   if (mf != NONE && glower) {
     const uint32_t mg = select_extremum(fd, G, fd.lab, s, glower, true);
-    if (mg != mf) mark_target(fd.tbits, sos_lt(F[mg], mg, F[mf], mf) ? mg : mf);
+    if (mg != mf) mark_target(fd.tmark, sos_lt(F[mg], mg, F[mf], mf) ? mg : mf);
   }
   const uint32_t gupper = vm & ~glower;
   if (Mf != NONE && gupper) {
     const uint32_t Mg = select_extremum(fd, G, fd.lab, s, gupper, false);
-    if (Mg != Mf) mark_target(fd.tbits, sos_lt(F[Mg], Mg, F[Mf], Mf) ? Mg : Mf);
+    if (Mg != Mf) mark_target(fd.tmark, sos_lt(F[Mg], Mg, F[Mf], Mf) ? Mg : Mf);
   }
 }
 

@@ -126,15 +126,13 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd, const uint8_
     if (fd.g != fd.g_hat) ((T *)fd.g)[i] = gi;
     if (!fd.resume) fd.cnt[i] = 0;
   }
+  if (active) fd.tmark[i] = 0;
   if (i < (uint32_t)fd.ntiles) fd.bdirty[i] = 0;  // ntiles <= n
-  // one 64-bit word of the CP bitmask per wave (waves cover aligned chunks);
-  // the same wave clears its 64 bits of the target set
+  // one 64-bit word of the CP bitmask per wave (waves cover aligned chunks)
   const unsigned long long b = __ballot(cp);
   if ((threadIdx.x & 63) == 0 && active) {
     fd.cpbits[i >> 6] = b;
     fd.cpoff[i >> 6] = (uint32_t)__popcll(b);
-    fd.tbits[2 * (i >> 6)] = 0;
-    fd.tbits[2 * (i >> 6) + 1] = 0;
   }
 }
 

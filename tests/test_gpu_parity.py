@@ -170,7 +170,7 @@ def test_error_statuses(ctx):
         ctx.correct(_dev(f), _dev(f), 0.1, n_steps=0)
 
 
-BOX_SHAPES = [(1, 1), (2, 2), (4, 1), (4, 2), (8, 1), (8, 2), (8, 4), (4, 8), (16, 1), (16, 2)]
+BOX_SHAPES = [(1, 1), (2, 2), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2), (4, 8), (16, 1), (16, 2)]
 
 
 @pytest.mark.parametrize("tile_y,tile_z", BOX_SHAPES)
@@ -182,7 +182,7 @@ def test_tile_shape_invariance(ctx, tile_y, tile_z):
     try:
         out, cout, r = ctx.correct(f, g, c.xi)
     finally:
-        ctx.set_option("tile", 404)
+        ctx.set_option("tile", 0)
     torch.cuda.synchronize()
     assert torch.equal(out, ref) and torch.equal(cout, cref)
     assert r["iterations"] == rref["iterations"]
@@ -344,7 +344,7 @@ def test_frontier_box_shapes(ctx, tile):
     try:
         out, cout, r = ctx.correct(f, g, c.xi)
     finally:
-        ctx.set_option("tile", 404)
+        ctx.set_option("tile", 0)
     torch.cuda.synchronize()
     assert torch.equal(out, ref) and torch.equal(cout, cref)
     assert (r["iterations"], r["status"], r["residual_violations"]) == (
