@@ -124,7 +124,7 @@ exz_status exz_ctx_destroy(exz_ctx *ctx);
  *              hipGraph (batched calls; default 1);
  *   "tile"     check box 64 x tile_y x tile_z given as tile_y * 100 + tile_z;
  *              compiled boxes (y, z): (1,1) (2,2) (4,1) (4,2) (4,4) (8,1)
- *              (8,2) (8,4) (4,8) (16,1) (16,2); 0 (default) picks 8 x 4 for
+ *              (8,2) (8,4) (4,8) (16,1) (16,2); 0 (default) picks 4 x 8 for
  *              volumes, 16 x 1 for planes and 1 x 1 for lines.  "tile_y" and
  *              "tile_z" set one side;
  *   "grid"     check work-groups: -1 persistent (default), 0 one per box,

@@ -92,12 +92,12 @@ struct Busy {
 
 namespace exz {
 
-// Box shape when none is set: 64 x 8 x 4 for volumes, 64 x 16 rows for
+// Box shape when none is set: 64 x 4 x 8 for volumes, 64 x 16 rows for
 // planes, single rows for lines (taller boxes would leave threads idle).
 void default_box(int ny, int nz, int &ty, int &tz) {
   if (nz > 1) {
-    ty = 8;
-    tz = 4;
+    ty = 4;
+    tz = 8;
   } else if (ny > 1) {
     ty = 16;
     tz = 1;
@@ -182,7 +182,7 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
   off[1] = L.add(3 * n);                                     // code, low
   off[2] = L.add(8 * (size_t)fd.nchunk);                     // cpbits
   off[3] = L.add(4 * ((size_t)fd.nchunk + 1));               // cpoff
-  off[4] = L.add(n);                                         // target marks
+  off[4] = L.add(n + 64);  // target marks (+ zero padding: marks are read four at a time)
   off[5] = L.add(4 * n);                                     // rank_of
   off[6] = own_cnt ? L.add(n) : 0;                           // cnt
   off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
@@ -234,6 +234,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   fd.bdirty = (uint8_t *)(base + oa[8]);
   fd.rank_of = (uint32_t *)(base + oa[5]);
   fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
+  fd.vec = quad_aligned(fd);
   uint32_t *scan_tmp = (uint32_t *)(base + oa[7]);
 
   HIP_OR_FAIL(launch_state_reset(fd, max_iters, s));

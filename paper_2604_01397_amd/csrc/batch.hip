@@ -30,76 +30,102 @@ struct ItemList {
   const uint32_t *base;       // [nfields + 1] item prefix
 };
 
-// Field slot of item `it` (largest k with base[k] <= it).
-__device__ __forceinline__ uint32_t find_field(const uint32_t *base, uint32_t nf, uint32_t it) {
-  uint32_t lo = 0, hi = nf;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (base[mid] <= it) lo = mid;
-    else hi = mid;
-  }
-  return lo;
+// Field slot of item `it` (largest k with base[k] <= it), found by walking
+// forward from slot k: a block (or thread) visits its items in increasing
+// order, so the walk is short and reads a few cached words.
+__device__ __forceinline__ uint32_t next_field(const uint32_t *base, uint32_t nf, uint32_t it,
+                                               uint32_t k) {
+  while (k + 1 < nf && base[k + 1] <= it) ++k;
+  return k;
 }
 
-template <int TY, int TZ>
+// The same for a whole work-group (it is the same on every lane): the slot
+// is made explicitly wave-uniform so the field's descriptor is read with
+// scalar loads.
+__device__ __forceinline__ uint32_t next_field_uniform(const uint32_t *base, uint32_t nf,
+                                                       uint32_t it, uint32_t k) {
+  return __builtin_amdgcn_readfirstlane(next_field(base, nf, it, k));
+}
+
+// Check passes over the boxes of fields of one value type T.
+template <class T, int TY, int TZ>
 __global__ void __launch_bounds__(64 * TY)
-    k_check_batch(const FieldDev *fields, const uint32_t *lists, const uint32_t *conn) {
-  __shared__ union {
-    CheckLds<float, TY, TZ> f;
-    CheckLds<double, TY, TZ> d;
-  } L;
+    k_check_batch(const FieldDev *__restrict__ fields, const uint32_t *__restrict__ lists,
+                  const uint32_t *__restrict__ conn) {
+  __shared__ CheckLds<T, TY, TZ> L;
   const uint32_t nf = lists[0], total = lists[1];
   const uint32_t *field = lists + 2, *base = lists + 2 + nf;
+  uint32_t k = 0;
   for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const uint32_t k = find_field(base, nf, it);
-    const FieldDev &fd = fields[field[k]];
-    if (!fd.st->done) {
-      const BoxOrigin o = box_of(fd, it - base[k], TY, TZ);
-      if (fd.dtype == 0)
-        check_box<float, TY, TZ>(fd, conn, o, L.f);
-      else
-        check_box<double, TY, TZ>(fd, conn, o, L.d);
+    k = next_field_uniform(base, nf, it, k);
+    const FieldDev &fd = fields[__builtin_amdgcn_readfirstlane(field[k])];
+    const uint32_t tile = it - base[k];
+    const State *st = fd.st;
+    // frontier passes skip boxes the last apply did not touch (and clear
+    // the flag of those they take); every thread reads the same flag
+    bool take = !st->done;
+    if (take && fd.frontier && !st->dense) take = fd.bdirty[tile] != 0;
+    if (take) {
+      if (fd.frontier && !st->dense) {
+        __syncthreads();  // every thread has read the flag
+        if (threadIdx.x == 0 && threadIdx.y == 0) fd.bdirty[tile] = 0;
+      }
+      check_box<T, TY, TZ>(fd, conn, box_of(fd, tile, TY, TZ), L);
     }
     __syncthreads();
   }
 }
+
+// Vertices of one batched apply item: sixteen quads per thread, so the
+// item's set-up (finding its field, reading its descriptor) is amortised.
+constexpr uint32_t APPLY_ITEM_QUADS = 16 * APPLY_BLOCK;
 
 // ApplyBoundedEdits: field k owns items [base[k], base[k+1]), one per
-// APPLY_CHUNK vertices.
-__global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *fields,
-                                                             const uint32_t *lists) {
+// 4 * APPLY_ITEM_QUADS vertices.
+__global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *__restrict__ fields,
+                                                             const uint32_t *__restrict__ lists) {
   const uint32_t nf = lists[0], total = lists[1];
   const uint32_t *field = lists + 2, *base = lists + 2 + nf;
+  // counts are added to a field's shards when the block moves on to the
+  // next field (items of one field are consecutive)
+  uint32_t k = 0, kc = 0;
+  EditCount ec = {{0, 0, 0, 0, 0}};
   for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const uint32_t k = find_field(base, nf, it);
-    const FieldDev &fd = fields[field[k]];
-    if (!fd.st->done) {
-      EditCount ec = {{0, 0, 0, 0, 0}};
-      const uint32_t v = (it - base[k]) * APPLY_CHUNK;
-      if (fd.dtype == 0)
-        apply_chunk<float>(fd, v, ec);
-      else
-        apply_chunk<double>(fd, v, ec);
-      flush_counts<APPLY_BLOCK / 64>(fd.st, ec, it);
+    k = next_field_uniform(base, nf, it, k);
+    if (k != kc) {
+      flush_counts<APPLY_BLOCK / 64>(fields[field[kc]].st, ec, blockIdx.x);
+      ec = EditCount{{0, 0, 0, 0, 0}};
+      kc = k;
     }
-    __syncthreads();
+    const FieldDev &fd = fields[__builtin_amdgcn_readfirstlane(field[k])];
+    if (!fd.st->done) {
+      const uint32_t q0 = (it - base[k]) * APPLY_ITEM_QUADS;
+      const uint32_t nq = min(((uint32_t)fd.n + 3) / 4, q0 + APPLY_ITEM_QUADS);
+      if (fd.dtype == 0)
+        apply_quads<float>(fd, q0 + threadIdx.x, APPLY_BLOCK, nq, ec);
+      else
+        apply_quads<double>(fd, q0 + threadIdx.x, APPLY_BLOCK, nq, ec);
+    }
   }
+  if (nf) flush_counts<APPLY_BLOCK / 64>(fields[field[kc]].st, ec, blockIdx.x);
 }
 
-// Critical-point pairs: field k owns items [base[k], base[k+1]) = its K - 1
-// consecutive pairs.
-__global__ void __launch_bounds__(256) k_cpcmp_batch(const FieldDev *fields, const uint32_t *lists) {
+// Critical-point pairs: field k owns items [base[k], base[k+1]), one per
+// four consecutive pairs.
+__global__ void __launch_bounds__(256) k_cpcmp_batch(const FieldDev *__restrict__ fields,
+                                                     const uint32_t *__restrict__ lists) {
   const uint32_t nf = lists[0], total = lists[1];
   const uint32_t *field = lists + 2, *base = lists + 2 + nf;
+  uint32_t k = 0;
   for (uint32_t it = blockIdx.x * 256 + threadIdx.x; it < total; it += gridDim.x * 256) {
-    const uint32_t k = find_field(base, nf, it);
+    k = next_field(base, nf, it, k);
     const FieldDev &fd = fields[field[k]];
     if (fd.st->done) continue;
-    const uint32_t r = it - base[k];
+    const uint32_t j = it - base[k];
     if (fd.dtype == 0)
-      cp_pair<float>(fd, r);
+      cp_quad<float>(fd, j);
     else
-      cp_pair<double>(fd, r);
+      cp_quad<double>(fd, j);
   }
 }
 
@@ -157,7 +183,7 @@ namespace exz {
 
 // Launch geometry shared by all members of a batch.
 struct BatchShape {
-  int ty3 = 8, tz3 = 4;  // boxes for 3D fields
+  int ty3 = 4, tz3 = 8;  // boxes for 3D fields
   int ty2 = 16, tz2 = 1; // boxes for 1D/2D fields
 };
 
@@ -186,18 +212,21 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
 
 }  // namespace exz
 
-// Device list buffers: NLISTS lists (check3, check2, cp, finalize, apply),
-// capacity per list 2 + 2*nf + 1 words.
-constexpr int NLISTS = 5;
+// Device list buffers, capacity per list 2 + 2*nf + 1 words: boxes of 3D
+// float32 / 3D float64 / 2D-1D float32 / 2D-1D float64 fields, critical-point
+// quads, finalize (one item per field), apply chunks.
+enum { L_BOX3F, L_BOX3D, L_BOX2F, L_BOX2D, L_CP, L_FIN, L_APPLY, NLISTS };
 static size_t list_words(size_t nf) { return 2 + 2 * nf + 1; }
 
 namespace exz {
 
+template <class T>
 static void box_launch_check(int ty, int tz, const FieldDev *fields, const uint32_t *list,
                              const uint32_t *conn, int grid, hipStream_t s) {
 #define EXZ_BOX_CHECK_B(a, b)                                                                 \
   if (ty == a && tz == b)                                                                     \
-    hipLaunchKernelGGL((k_check_batch<a, b>), dim3(grid), dim3(64, a), 0, s, fields, list, conn);
+    hipLaunchKernelGGL((k_check_batch<T, a, b>), dim3(grid), dim3(64, a), 0, s, fields, list, \
+                       conn);
   EXZ_BOX_SHAPES(EXZ_BOX_CHECK_B)
 #undef EXZ_BOX_CHECK_B
 }
@@ -206,20 +235,59 @@ static void box_launch_check(int ty, int tz, const FieldDev *fields, const uint3
 static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dlists, size_t lw,
                              const BatchShape &shape, int iters, int grid_box, int grid_cp,
                              int grid_fin, int grid_apply, hipStream_t s) {
-  uint32_t *l3 = dlists, *l2 = dlists + lw, *lc = dlists + 2 * lw, *lf = dlists + 3 * lw,
-           *la = dlists + 4 * lw;
+  auto list = [&](int q) { return dlists + q * lw; };
+  uint32_t *lc = list(L_CP), *lf = list(L_FIN), *la = list(L_APPLY);
   for (int it = 0; it < iters; ++it) {
-    box_launch_check(shape.ty3, shape.tz3, fields, l3, ctx->d_conn, grid_box, s);
-    box_launch_check(shape.ty2, shape.tz2, fields, l2, ctx->d_conn, grid_box, s);
+    box_launch_check<float>(shape.ty3, shape.tz3, fields, list(L_BOX3F), ctx->d_conn, grid_box, s);
+    box_launch_check<double>(shape.ty3, shape.tz3, fields, list(L_BOX3D), ctx->d_conn, grid_box, s);
+    box_launch_check<float>(shape.ty2, shape.tz2, fields, list(L_BOX2F), ctx->d_conn, grid_box, s);
+    box_launch_check<double>(shape.ty2, shape.tz2, fields, list(L_BOX2D), ctx->d_conn, grid_box, s);
     hipLaunchKernelGGL(k_cpcmp_batch, dim3(grid_cp), dim3(256), 0, s, fields, lc);
     hipLaunchKernelGGL(k_apply_batch, dim3(grid_apply), dim3(APPLY_BLOCK), 0, s, fields, la);
     hipLaunchKernelGGL(k_finalize_batch, dim3(grid_fin), dim3(64), 0, s, fields, lf);
   }
 }
 
-// Items of the apply pass of one field: APPLY_CHUNK vertices each.
+static uint32_t cp_items(const FieldDev &fd);
+static uint32_t apply_items(const FieldDev &fd);
+
+// Host item lists of one batched iteration over the fields fds[k] with
+// active[k], written into the pinned buffer hl (NLISTS lists of lw words).
+static void build_lists(const std::vector<const FieldDev *> &fds, const std::vector<bool> &active,
+                        uint32_t *hl, size_t lw) {
+  std::vector<int> f[NLISTS];
+  std::vector<uint32_t> n[NLISTS];
+  for (size_t k = 0; k < fds.size(); ++k) {
+    if (!active[k]) continue;
+    const FieldDev &fd = *fds[k];
+    const int idx = (int)k;
+    const int box = fd.nz > 1 ? (fd.dtype == 0 ? L_BOX3F : L_BOX3D)
+                              : (fd.dtype == 0 ? L_BOX2F : L_BOX2D);
+    f[box].push_back(idx);
+    n[box].push_back((uint32_t)fd.ntiles);
+    f[L_CP].push_back(idx);
+    n[L_CP].push_back(cp_items(fd));
+    f[L_FIN].push_back(idx);
+    n[L_FIN].push_back(1);
+    f[L_APPLY].push_back(idx);
+    n[L_APPLY].push_back(apply_items(fd));
+  }
+  for (int q = 0; q < NLISTS; ++q) {
+    Lists L;
+    L.build(f[q], n[q]);
+    std::memcpy(hl + q * lw, L.v.data(), L.v.size() * 4);
+  }
+}
+
+// Items of the critical-point compare of one field: four pairs each.
+static uint32_t cp_items(const FieldDev &fd) {
+  return fd.K > 1 ? (uint32_t)((fd.K - 1 + 3) / 4) : 0u;
+}
+
+// Items of the apply pass of one field: 4 * APPLY_ITEM_QUADS vertices each.
 static uint32_t apply_items(const FieldDev &fd) {
-  return (uint32_t)(((uint32_t)fd.n + APPLY_CHUNK - 1) / APPLY_CHUNK);
+  const uint32_t nq = ((uint32_t)fd.n + 3) / 4;
+  return (nq + APPLY_ITEM_QUADS - 1) / APPLY_ITEM_QUADS;
 }
 
 exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *dev_fields,
@@ -248,7 +316,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   uint64_t max_boxes = 0, max_cp = 0, max_apply = 0;
   for (auto &m : members) {
     max_boxes += (uint64_t)m.fd.ntiles;
-    max_cp += m.fd.K > 1 ? (uint64_t)(m.fd.K - 1) : 0;
+    max_cp += cp_items(m.fd);
     max_apply += apply_items(m.fd);
   }
   const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_boxes, 256 * 8));
@@ -260,28 +328,16 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   int grid_fin = (int)nf;
   for (int round = 0; round < max_chunks; ++round) {
     // item lists over the active members
-    std::vector<int> f3, f2, fc, fa;
-    std::vector<uint32_t> i3, i2, ic, ia, iw;
+    std::vector<const FieldDev *> fds(nf);
+    std::vector<bool> act(nf);
+    bool any = false;
     for (size_t k = 0; k < nf; ++k) {
-      const Member &m = members[k];
-      if (!m.active) continue;
-      const int idx = (int)k;
-      (m.fd.nz > 1 ? f3 : f2).push_back(idx);
-      (m.fd.nz > 1 ? i3 : i2).push_back((uint32_t)m.fd.ntiles);
-      fc.push_back(idx);
-      ic.push_back(m.fd.K > 1 ? (uint32_t)(m.fd.K - 1) : 0u);
-      fa.push_back(idx);
-      ia.push_back(1);
-      iw.push_back(apply_items(m.fd));
+      fds[k] = &members[k].fd;
+      act[k] = members[k].active;
+      any |= act[k];
     }
-    if (fa.empty()) break;
-    Lists L[NLISTS];
-    L[0].build(f3, i3);
-    L[1].build(f2, i2);
-    L[2].build(fc, ic);
-    L[3].build(fa, ia);
-    L[4].build(fa, iw);
-    for (int q = 0; q < NLISTS; ++q) std::memcpy(hl + q * lw, L[q].v.data(), L[q].v.size() * 4);
+    if (!any) break;
+    build_lists(fds, act, hl, lw);
     HIP_OR_FAIL_B(hipMemcpyAsync(dlists, hl, NLISTS * lw * sizeof(uint32_t),
                                  hipMemcpyHostToDevice, s));
     if (ctx->graph) {
@@ -305,9 +361,9 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
                          grid_apply, s);
       HIP_OR_FAIL_B(hipGetLastError());
     }
-    for (size_t k = 0; k < nf; ++k)
-      HIP_OR_FAIL_B(hipMemcpyAsync(hstates + k, members[k].fd.st, sizeof(State),
-                                   hipMemcpyDeviceToHost, s));
+    // the members' states are consecutive (one array, slot k = member k)
+    HIP_OR_FAIL_B(hipMemcpyAsync(hstates, members[0].fd.st, nf * sizeof(State),
+                                 hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL_B(hipStreamSynchronize(s));
     for (size_t k = 0; k < nf; ++k)
       if (members[k].active && hstates[k].done != RUNNING) members[k].active = false;
@@ -393,7 +449,6 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     m.fd.tiles_y = (m.fd.ny + m.fd.tile_y - 1) / m.fd.tile_y;
     m.fd.tiles_z = (m.fd.nz + m.fd.tile_z - 1) / m.fd.tile_z;
     m.fd.ntiles = m.fd.tiles_x * m.fd.tiles_y * m.fd.tiles_z;
-    m.fd.frontier = 0;  // batched check passes cover every box
     m.fd.f = fl.f;
     m.fd.g_hat = fl.g_hat;
     m.fd.g = fl.g_out;
@@ -439,6 +494,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.rank_of = (uint32_t *)(b + oa[k][5]);
       uint8_t *cnt_io = fields[mem[k].index].cnt_io;
       fd.cnt = cnt_io ? cnt_io : (uint8_t *)(b + oa[k][6]);
+      fd.vec = quad_aligned(fd);
       uint32_t *scan_tmp = (uint32_t *)(b + oa[k][7]);
       HIP_OR_FAIL_B(launch_state_reset(fd, mem[k].max_iters, s));
       HIP_OR_FAIL_B(launch_setup(fd, ctx->d_comp, s));
@@ -603,7 +659,6 @@ exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, ex
     fd.tiles_y = (fd.ny + fd.tile_y - 1) / fd.tile_y;
     fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
     fd.ntiles = fd.tiles_x * fd.tiles_y * fd.tiles_z;
-    fd.frontier = 0;  // batched check passes cover every box
     st = setup_field(ctx, fd, field->f, field->g_hat, field->g_out, field->cnt_io,
                      field->params.max_iters, job->A, job->B, (hipStream_t)stream);
   }
@@ -643,32 +698,20 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   }
   FieldDev *hf = (FieldDev *)ctx->step_host;
   uint32_t *hl = (uint32_t *)(hf + nf);
-  std::vector<int> f3, f2, fc, fa;
-  std::vector<uint32_t> i3, i2, ic, ia, iw;
   uint64_t boxes = 0, cps = 0, words = 0;
+  std::vector<const FieldDev *> fds(nf);
+  std::vector<bool> act(nf, true);
   for (size_t k = 0; k < nf; ++k) {
     if (!jobs[k]) return fail_b(ctx, EXZ_E_INVALID, "null job");
     hf[k] = jobs[k]->fd;
     const FieldDev &fd = hf[k];
-    (fd.nz > 1 ? f3 : f2).push_back((int)k);
-    (fd.nz > 1 ? i3 : i2).push_back((uint32_t)fd.ntiles);
-    fc.push_back((int)k);
-    ic.push_back(fd.K > 1 ? (uint32_t)(fd.K - 1) : 0u);
-    fa.push_back((int)k);
-    ia.push_back(1);
-    iw.push_back(apply_items(fd));
+    fds[k] = &hf[k];
     words += apply_items(fd);
     boxes += (uint64_t)fd.ntiles;
-    cps += fd.K > 1 ? (uint64_t)(fd.K - 1) : 0;
+    cps += cp_items(fd);
     jobs[k]->last = s;
   }
-  Lists L[NLISTS];
-  L[0].build(f3, i3);
-  L[1].build(f2, i2);
-  L[2].build(fc, ic);
-  L[3].build(fa, ia);
-  L[4].build(fa, iw);
-  for (int q = 0; q < NLISTS; ++q) std::memcpy(hl + q * lw, L[q].v.data(), L[q].v.size() * 4);
+  build_lists(fds, act, hl, lw);
   FieldDev *df = (FieldDev *)ctx->step_dev;
   uint32_t *dl = (uint32_t *)(df + nf);
   HIP_OR_FAIL_B(hipMemcpyAsync(df, hf, bytes, hipMemcpyHostToDevice, s));

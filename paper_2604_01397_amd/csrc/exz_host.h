@@ -32,6 +32,12 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
 exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
                             uint8_t *cnt_io, const exz_params *params, exz_result *res,
                             hipStream_t s);
+// f and g 16-byte aligned and the counts 4-byte aligned (apply may then
+// read a quad of vertices with vector loads).
+inline int quad_aligned(const FieldDev &fd) {
+  return ((uintptr_t)fd.f % 16 == 0) && ((uintptr_t)fd.g % 16 == 0) && ((uintptr_t)fd.cnt % 4 == 0);
+}
+
 void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, Layout &L,
               size_t off[9]);
 void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]);

@@ -76,6 +76,7 @@ struct FieldDev {
   int32_t trace_cap;
   int32_t frontier;     // 1: re-check only boxes whose closed neighbourhood changed
   int32_t ty_shift, tz_shift;  // log2 of tile_y / tile_z
+  int32_t vec;          // f, g 16-byte and cnt 4-byte aligned: apply reads four vertices at once
   int32_t dlt[16];      // linear index offset of each slot (dlt[SELF] = 0)
   double xiT, delta;    // in the field type, widened exactly to double
   const void *f;
@@ -103,10 +104,19 @@ struct FieldDev {
 // ---------------------------------------------------------------------------
 // device helpers
 
+// Device pointers read out of a descriptor in memory (the batched kernels)
+// have no address space, so accesses through them compile to flat
+// instructions, which also hold the LDS wait counter.  glob() states that a
+// pointer is global memory; for kernel arguments it changes nothing.
+template <class P>
+__device__ __forceinline__ __attribute__((address_space(1))) P *glob(P *p) {
+  return (__attribute__((address_space(1))) P *)p;
+}
+
 // Adds vertex t to the target set: a plain byte store (every writer stores
 // the same value, so concurrent marks of one target need no atomics; the
 // cache keeps per-byte dirty masks, so neighbouring marks do not clash).
-__device__ __forceinline__ void mark_target(uint8_t *marks, uint32_t t) { marks[t] = 1; }
+__device__ __forceinline__ void mark_target(uint8_t *marks, uint32_t t) { glob(marks)[t] = 1; }
 
 // Simulation of Simplicity: (a, ia) < (b, ib).  Bitwise, not short-circuit,
 // so that the compiler emits straight-line compares instead of branches.

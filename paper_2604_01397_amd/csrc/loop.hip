@@ -101,23 +101,23 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
 }
 
-// Critical-point order: every consecutive pair, one thread each.
+// Critical-point order: every consecutive pair, four per thread.
 constexpr int CP_BLOCK = 256;
 
 template <class T>
 __global__ void __launch_bounds__(CP_BLOCK) k_cpcmp(FieldDev fd) {
   if (fd.st->done) return;
-  const uint32_t k = blockIdx.x * CP_BLOCK + threadIdx.x;
-  if (k + 1 < (uint32_t)fd.K) cp_pair<T>(fd, k);
+  const uint32_t j = blockIdx.x * CP_BLOCK + threadIdx.x;
+  if (4u * j + 1 < (uint32_t)fd.K) cp_quad<T>(fd, j);
 }
 
-// ApplyBoundedEdits over the target marks, chunks of APPLY_CHUNK vertices.
+// ApplyBoundedEdits over the target marks.
 template <class T>
 __global__ void __launch_bounds__(APPLY_BLOCK) k_apply(FieldDev fd) {
   if (fd.st->done) return;
-  const uint32_t nchunks = ((uint32_t)fd.n + APPLY_CHUNK - 1) / APPLY_CHUNK;
+  const uint32_t nq = ((uint32_t)fd.n + 3) / 4;
   EditCount ec = {{0, 0, 0, 0, 0}};
-  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) apply_chunk<T>(fd, c * APPLY_CHUNK, ec);
+  apply_quads<T>(fd, blockIdx.x * APPLY_BLOCK + threadIdx.x, gridDim.x * APPLY_BLOCK, nq, ec);
   flush_counts<APPLY_BLOCK / 64>(fd.st, ec, blockIdx.x);
 }
 
@@ -175,14 +175,14 @@ static void launch_check_cpcmp(const FieldDev &fd, const uint32_t *conn, const u
   if (fd.mode == 1)
     (void)launch_original_events(fd, comp, s);
   else if (fd.K > 1)
-    hipLaunchKernelGGL(k_cpcmp<T>, dim3((fd.K - 1 + CP_BLOCK - 1) / CP_BLOCK), dim3(CP_BLOCK), 0, s,
-                       fd);
+    hipLaunchKernelGGL(k_cpcmp<T>, dim3((fd.K - 1 + 4 * CP_BLOCK - 1) / (4 * CP_BLOCK)),
+                       dim3(CP_BLOCK), 0, s, fd);
 }
 
 template <class T>
 static void launch_apply(const FieldDev &fd, hipStream_t s) {
   const int chunks = (int)(((uint32_t)fd.n + APPLY_CHUNK - 1) / APPLY_CHUNK);
-  hipLaunchKernelGGL(k_apply<T>, dim3(std::min(chunks, 16384)), dim3(APPLY_BLOCK), 0, s, fd);
+  hipLaunchKernelGGL(k_apply<T>, dim3(std::min(chunks, 8192)), dim3(APPLY_BLOCK), 0, s, fd);
 }
 
 template <class T>

@@ -70,7 +70,7 @@ __device__ __forceinline__ void stage_rows(const FieldDev &fd, const V *__restri
     r[k] = outside_value<V>();
     if (row_in) {  // uniform across the wave
       const V *rp = src + ((uint32_t)gz * (uint32_t)ny + (uint32_t)gy) * (uint32_t)nx;
-      const V v = rp[inner_x ? (uint32_t)xl : cxl];
+      const V v = glob(rp)[inner_x ? (uint32_t)xl : cxl];
       r[k] = (inner_x || in_x) ? v : outside_value<V>();
     }
   }
@@ -84,7 +84,7 @@ __device__ __forceinline__ void stage_rows(const FieldDev &fd, const V *__restri
     const bool in = t < 2 * NR && gy >= 0 && gy < ny && gz >= 0 && gz < nz && gx < nx;
     const uint32_t cy = (uint32_t)min(max(gy, 0), ny - 1), cz = (uint32_t)min(max(gz, 0), nz - 1);
     const uint32_t cx = (uint32_t)min(gx, nx - 1);
-    const V v = src[(cz * (uint32_t)ny + cy) * (uint32_t)nx + cx];
+    const V v = glob(src)[(cz * (uint32_t)ny + cy) * (uint32_t)nx + cx];
     e[k] = in ? v : outside_value<V>();
   }
 #pragma unroll
@@ -220,7 +220,7 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__
   for (int k = 0; k < TZ; ++k) {  // issued with the staging loads, unconditionally
     const bool in = col && o.z0 + k < fd.nz;
     const uint32_t idx = in ? i0 + k * plane : 0u;
-    const uint32_t cb = fd.code[idx], lb = fd.low[idx];
+    const uint32_t cb = glob(fd.code)[idx], lb = glob(fd.low)[idx];
     refs[k] = cb | (lb << 8);
   }
   stage_rows<TY, TZ>(fd, (const T *)fd.g, L.S, o);
@@ -241,8 +241,8 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__
                                          rf >> 8, av, dv, interior);
       if (r) post_targets(fd, i, r);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
-        fd.lab[i] = dv;
-        fd.lab[fd.n + i] = (uint32_t)fd.n + av;
+        glob(fd.lab)[i] = dv;
+        glob(fd.lab)[fd.n + i] = (uint32_t)fd.n + av;
       }
     }
   }
@@ -252,12 +252,51 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__
 // must keep their order in g; an inverted pair decreases the lower one.
 // Values are finite, so b > a settles most pairs without the vertex indices.
 template <class T>
+__device__ __forceinline__ void cp_pair_vals(const FieldDev &fd, uint32_t r, T a, T b) {
+  if (b > a) return;
+  const uint32_t ia = glob(fd.cp_idx)[r], ib = glob(fd.cp_idx)[r + 1];
+  if (sos_lt(b, ib, a, ia)) mark_target(fd.tmark, ia);
+}
+
+template <class T>
 __device__ __forceinline__ void cp_pair(const FieldDev &fd, uint32_t r) {
   const T *V = (const T *)fd.cp_val;
-  const T a = V[r], b = V[r + 1];
-  if (b > a) return;
-  const uint32_t ia = fd.cp_idx[r], ib = fd.cp_idx[r + 1];
-  if (sos_lt(b, ib, a, ia)) mark_target(fd.tmark, ia);
+  cp_pair_vals<T>(fd, r, glob(V)[r], glob(V)[r + 1]);
+}
+
+// Pairs 4j .. 4j+3 (those with a successor): five values, read as one
+// aligned block of four plus the next one.
+template <class T> struct Vec4;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <> struct Vec4<float> {
+  static __device__ __forceinline__ void load(const float *p, float *o) {
+    const f32x4 v = *glob(reinterpret_cast<const f32x4 *>(p));
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+};
+template <> struct Vec4<double> {
+  static __device__ __forceinline__ void load(const double *p, double *o) {
+    const f64x2 a = glob(reinterpret_cast<const f64x2 *>(p))[0];
+    const f64x2 b = glob(reinterpret_cast<const f64x2 *>(p))[1];
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  }
+};
+
+template <class T>
+__device__ __forceinline__ void cp_quad(const FieldDev &fd, uint32_t j) {
+  const T *V = (const T *)fd.cp_val;
+  const uint32_t K = (uint32_t)fd.K, r0 = 4u * j;
+  T v[5];
+  if (r0 + 4 < K) {
+    Vec4<T>::load(V + r0, v);
+    v[4] = glob(V)[r0 + 4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cp_pair_vals<T>(fd, r0 + k, v[k], v[k + 1]);
+  } else {
+    for (uint32_t r = r0; r + 1 < K; ++r) cp_pair<T>(fd, r);
+  }
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -287,99 +326,118 @@ __device__ __forceinline__ void mark_box_range(const FieldDev &fd, uint32_t x0, 
   for (uint32_t bz = bz0; bz <= bz1; ++bz)
     for (uint32_t by = by0; by <= by1; ++by)
       for (uint32_t bx = bx0; bx <= bx1; ++bx)
-        fd.bdirty[bx + (uint32_t)fd.tiles_x * (by + (uint32_t)fd.tiles_y * bz)] = 1;
+        glob(fd.bdirty)[bx + (uint32_t)fd.tiles_x * (by + (uint32_t)fd.tiles_y * bz)] = 1;
 }
 
-// Box marks for the vertices of a 64-vertex run (run_base + lane) set in
-// the wave-uniform mask `moved`: one range when they lie on one grid row
-// (marked by lane 0), else each moving lane marks its own vertex.
-__device__ __forceinline__ void mark_run_boxes(const FieldDev &fd, uint32_t run_base,
-                                               unsigned long long moved, bool mine) {
-  const uint32_t nx = (uint32_t)fd.nx, ny = (uint32_t)fd.ny;
-  const uint32_t lo = run_base + (uint32_t)(__ffsll(moved) - 1);
-  const uint32_t hi = run_base + 63u - (uint32_t)__clzll(moved);
-  const uint32_t x = lo % nx, r = lo / nx;
-  if (x + (hi - lo) < nx) {
-    if (__lane_id() == 0) mark_box_range(fd, x, x + (hi - lo), r % ny, r / ny);
-    return;
-  }
-  if (mine) {
-    const uint32_t t = run_base + __lane_id();
-    const uint32_t tx = t % nx, tr = t / nx;
-    mark_box_range(fd, tx, tx, tr % ny, tr / ny);
-  }
-}
-
-// Work-group size of the apply passes and the vertices one work-group
-// covers per chunk: each wave takes 256 consecutive vertices as four runs
-// of 64 (one vertex per lane, so every load and store is coalesced).
+// Work-group size of the apply passes.  A thread takes four consecutive
+// vertices (their marks are one 32-bit word), so a wave covers 256
+// consecutive vertices and a work-group APPLY_CHUNK.
 constexpr int APPLY_BLOCK = 256;
-constexpr uint32_t APPLY_CHUNK = 1024;
+constexpr uint32_t APPLY_CHUNK = 4 * APPLY_BLOCK;
 
-// ApplyBoundedEdits on the chunk starting at vertex `base`; clears the
-// marks it consumes and adds this thread's counts to ec.  A wave without a
-// marked vertex stops after reading its marks; otherwise the loads of all
-// its targets go out together.  In frontier mode the vertices whose value
-// or count moved mark the boxes that read them.
+// Target marks of vertices 4q .. 4q+3 (the mark array is padded).
+__device__ __forceinline__ uint32_t quad_marks(const FieldDev &fd, uint32_t q) {
+  return *glob(reinterpret_cast<const uint32_t *>(fd.tmark + 4u * q));
+}
+
+// ApplyBoundedEdits on the vertices v .. v+3 whose mark bytes in m are set
+// (m != 0); clears the marks and adds this thread's counts to ec.  The
+// loads of all four go out together (unmarked ones read vertex v, which is
+// valid).  Returns the vertices whose value or count moved, as bits 0..3.
 template <class T>
-__device__ __forceinline__ void apply_chunk(const FieldDev &fd, uint32_t base, EditCount &ec) {
-  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint32_t v0 = base + w * 256u + lane, n = (uint32_t)fd.n;
-  uint32_t mk[4];
-  bool any = false;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const uint32_t v = v0 + 64u * c;
-    mk[c] = v < n ? fd.tmark[v] : 0u;
-    any |= mk[c] != 0;
-  }
-  if (!__any(any)) return;
+__device__ __forceinline__ uint32_t apply_quad(const FieldDev &fd, uint32_t v, uint32_t m,
+                                               EditCount &ec) {
   T *G = (T *)fd.g;
   const T *F = (const T *)fd.f;
   const T xiT = (T)fd.xiT, delta = (T)fd.delta;
   T g0[4], fv[4];
   uint32_t c0[4], rk[4];
+  if (fd.vec && v + 3 < (uint32_t)fd.n) {  // whole quad: vector loads
+    Vec4<T>::load(G + v, g0);
+    Vec4<T>::load(F + v, fv);
+    const uint32_t c4 = *glob(reinterpret_cast<const uint32_t *>(fd.cnt + v));
+    const u32x4 r4 = *glob(reinterpret_cast<const u32x4 *>(fd.rank_of + v));
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {  // unmarked lanes read vertex 0, always valid
-    const uint32_t t = mk[c] ? v0 + 64u * c : 0u;
-    g0[c] = G[t];
-    fv[c] = F[t];
-    c0[c] = fd.cnt[t];
-    rk[c] = fd.rank_of[t];
+    for (int c = 0; c < 4; ++c) c0[c] = (c4 >> (8 * c)) & 255u;
+    rk[0] = r4.x;
+    rk[1] = r4.y;
+    rk[2] = r4.z;
+    rk[3] = r4.w;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t t = ((m >> (8 * c)) & 255u) ? v + c : v;
+      g0[c] = glob(G)[t];
+      fv[c] = glob(F)[t];
+      c0[c] = glob(fd.cnt)[t];
+      rk[c] = glob(fd.rank_of)[t];
+    }
   }
-  bool moved[4];
+  *glob(reinterpret_cast<uint32_t *>(fd.tmark + v)) = 0;
+  uint32_t moved = 0;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    moved[c] = false;
-    if (!mk[c]) continue;
-    const uint32_t t = v0 + 64u * c;
-    fd.tmark[t] = 0;
+    if (!((m >> (8 * c)) & 255u)) continue;
+    const uint32_t t = v + c;
     ++ec.v[0];
     const T L = lower_bound(fv[c], xiT);
     if (g0[c] == L) continue;  // at the floor: blocked
     const uint32_t cn = c0[c] + 1;
-    fd.cnt[t] = (uint8_t)cn;
-    T v;
+    glob(fd.cnt)[t] = (uint8_t)cn;
+    T nv;
     if (cn > (uint32_t)fd.N) {
-      v = L;  // (N+1)-th edit: store the lower bound itself
+      nv = L;  // (N+1)-th edit: store the lower bound itself
       ++ec.v[2];
     } else {
       const T cand = g0[c] - delta;
-      v = cand < L ? L : cand;
+      nv = cand < L ? L : cand;
     }
-    G[t] = v;
-    if (rk[c] != 0xFFFFFFFFu) ((T *)fd.cp_val)[rk[c]] = v;
-    moved[c] = true;
+    glob(G)[t] = nv;
+    if (rk[c] != 0xFFFFFFFFu) glob((T *)fd.cp_val)[rk[c]] = nv;
+    moved |= 1u << c;
     ++ec.v[1];
-    ec.v[3] += v == L;
+    ec.v[3] += nv == L;
     ec.v[4] += cn == 1;
   }
-  if (fd.frontier) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const unsigned long long b = __ballot(moved[c]);
-      if (b) mark_run_boxes(fd, v0 - lane + 64u * c, b, moved[c]);
-    }
+  return moved;
+}
+
+// Box marks for the vertices that moved in one wave (lane l moved the
+// vertices v + bits of `moved`; the wave's vertices are consecutive): one
+// range when they lie on one grid row (marked by one lane), else every
+// lane marks its own.  All lanes of the wave take part.
+__device__ __forceinline__ void mark_moved_boxes(const FieldDev &fd, uint32_t v, uint32_t moved) {
+  const unsigned long long b = __ballot(moved != 0);
+  if (!b) return;
+  const uint32_t first = v + (moved ? (uint32_t)(__ffs(moved) - 1) : 0u);
+  const uint32_t last = v + (moved ? 31u - (uint32_t)__clz(moved) : 0u);
+  const uint32_t lo = __shfl(first, __ffsll(b) - 1), hi = __shfl(last, 63 - __clzll(b));
+  const uint32_t nx = (uint32_t)fd.nx, ny = (uint32_t)fd.ny;
+  const uint32_t x = lo % nx, r = lo / nx;
+  if (x + (hi - lo) < nx) {
+    if (__lane_id() == (uint32_t)(__ffsll(b) - 1)) mark_box_range(fd, x, x + (hi - lo), r % ny, r / ny);
+    return;
+  }
+  while (moved) {
+    const uint32_t t = v + (uint32_t)(__ffs(moved) - 1);
+    moved &= moved - 1;
+    const uint32_t tx = t % nx, tr = t / nx;
+    mark_box_range(fd, tx, tx, tr % ny, tr / ny);
+  }
+}
+
+// ApplyBoundedEdits over quads q = q0, q0 + stride, ... (< nq): the marks of
+// the next quad are fetched before the current one is edited.
+template <class T>
+__device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uint32_t stride,
+                                            uint32_t nq, EditCount &ec) {
+  uint32_t m = q0 < nq ? quad_marks(fd, q0) : 0u;
+  for (uint32_t q = q0; q < nq; q += stride) {
+    const uint32_t qn = q + stride;
+    const uint32_t mn = qn < nq ? quad_marks(fd, qn) : 0u;
+    const uint32_t moved = m ? apply_quad<T>(fd, 4u * q, m, ec) : 0u;
+    if (fd.frontier) mark_moved_boxes(fd, 4u * q, moved);
+    m = mn;
   }
 }
 

@@ -127,6 +127,7 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd, const uint8_
     if (!fd.resume) fd.cnt[i] = 0;
   }
   if (active) fd.tmark[i] = 0;
+  if (i < 64) fd.tmark[(uint32_t)fd.n + i] = 0;  // padding
   if (i < (uint32_t)fd.ntiles) fd.bdirty[i] = 0;  // ntiles <= n
   // one 64-bit word of the CP bitmask per wave (waves cover aligned chunks)
   const unsigned long long b = __ballot(cp);

@@ -1,0 +1,46 @@
+"""Autotuner on the GPU: a quick tuning run stores an entry, every candidate
+reproduced the same result (the tuner checks it), and a tuned context
+corrects a field of that class exactly as the default one does."""
+import numpy as np
+import pytest
+
+from paper_2604_01397_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_then_correct(tmp_path):
+    from paper_2604_01397_amd import autotune, exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cache = str(tmp_path / "tune.json")
+    c = synth.case_grf3d(40, seed=51, rel=1e-3)
+    f = torch.from_numpy(c.f).cuda()
+    g = torch.from_numpy(c.g_hat).cuda()
+    ctx = exactz.Context(0)
+    try:
+        print("tuning", c.name, flush=True)
+        entry = autotune.tune(ctx, f, g, c.xi, quick=True, cache=cache, log=print)
+        assert entry["candidates"] == len(autotune.search_space(3, quick=True))
+        assert autotune.options_for(autotune.device_arch(0), 3, "f32", f.numel(), cache)
+        ref, cref, rref = ctx.correct(f, g, c.xi)
+    finally:
+        ctx.close()
+    tc = autotune.TunedContext(0, cache=cache)
+    try:
+        # a different field of the same class
+        c2 = synth.case_grf3d(41, seed=52, rel=1e-3)
+        f2, g2 = torch.from_numpy(c2.f).cuda(), torch.from_numpy(c2.g_hat).cuda()
+        out, cout, r = tc.correct(f2, g2, c2.xi)
+        plain = exactz.Context(0)
+        try:
+            o2, co2, r2 = plain.correct(f2, g2, c2.xi)
+        finally:
+            plain.close()
+        torch.cuda.synchronize()
+        assert torch.equal(out, o2) and torch.equal(cout, co2)
+        assert r["iterations"] == r2["iterations"]
+    finally:
+        tc.close()

@@ -349,3 +349,26 @@ def test_frontier_box_shapes(ctx, tile):
     assert torch.equal(out, ref) and torch.equal(cout, cref)
     assert (r["iterations"], r["status"], r["residual_violations"]) == (
         rref["iterations"], rref["status"], rref["residual_violations"])
+
+
+def test_unaligned_buffers_match(ctx):
+    """Buffers that are not 16-byte aligned take the apply's scalar loads;
+    the result must not change."""
+    for dtype in (np.float32, np.float64):
+        c = synth.case_grf3d((23, 30, 41), seed=41, rel=1e-3, dtype=dtype)
+        f, g = _dev(c.f), _dev(c.g_hat)
+        ref, cref, rref = ctx.correct(f, g, c.xi)
+        n = c.f.size
+        fb = torch.empty(n + 1, dtype=f.dtype, device="cuda")
+        gb = torch.empty(n + 1, dtype=f.dtype, device="cuda")
+        ob = torch.empty(n + 1, dtype=f.dtype, device="cuda")
+        cb = torch.zeros(n + 1, dtype=torch.uint8, device="cuda")
+        fu, gu = fb[1:].view(f.shape), gb[1:].view(f.shape)
+        ou, cu = ob[1:].view(f.shape), cb[1:].view(f.shape)
+        fu.copy_(f)
+        gu.copy_(g)
+        assert fu.data_ptr() % 16 != 0
+        out, cout, r = ctx.correct(fu, gu, c.xi, g_out=ou, cnt=cu)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref) and torch.equal(cout, cref)
+        assert r["iterations"] == rref["iterations"] and r["status"] == rref["status"]
