@@ -34,6 +34,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_check_512cube_f32_traffic.txt")
+
+
+def measured_traffic(edge):
+    """HBM bytes per k_check launch from the committed counter runs
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy kernel), or None if
+    the workload differs or the check kernel's sources changed since."""
+    import hashlib
+    if edge != 512 or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    with open(TRAFFIC_RECORD) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(case, edge=128):
     """Time the CPU oracle on an edge^3 sub-block of the workload."""
     import numpy as np
@@ -254,7 +275,7 @@ def main():
                    "loop_ms": round(res["loop_ms"], 3), "frontier": args.frontier},
         "roofline": {"bound": "hbm", "kernel": "k_check", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_ms": round(avg_check_ms, 5),
+                     "traffic": measured_traffic(args.edge), "avg_launch_ms": round(avg_check_ms, 5),
                      "launches": check_n, "bytes_per_launch": round(algo_bytes),
                      "vertices_checked_per_step": check_v // args.steps},
     }

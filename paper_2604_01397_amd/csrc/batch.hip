@@ -110,22 +110,27 @@ __global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *__r
   if (nf) flush_counts<APPLY_BLOCK / 64>(fields[field[kc]].st, ec, blockIdx.x);
 }
 
-// Critical-point pairs: field k owns items [base[k], base[k+1]), one per
-// four consecutive pairs.
+// Critical-point pairs in quads of four; one item is CP_ITEM_QUADS quads
+// of one field (field k owns items [base[k], base[k+1])).
+constexpr uint32_t CP_ITEM_QUADS = 4 * 256;
+
 __global__ void __launch_bounds__(256) k_cpcmp_batch(const FieldDev *__restrict__ fields,
                                                      const uint32_t *__restrict__ lists) {
   const uint32_t nf = lists[0], total = lists[1];
   const uint32_t *field = lists + 2, *base = lists + 2 + nf;
   uint32_t k = 0;
-  for (uint32_t it = blockIdx.x * 256 + threadIdx.x; it < total; it += gridDim.x * 256) {
-    k = next_field(base, nf, it, k);
-    const FieldDev &fd = fields[field[k]];
+  for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+    k = next_field_uniform(base, nf, it, k);
+    const FieldDev &fd = fields[__builtin_amdgcn_readfirstlane(field[k])];
     if (fd.st->done) continue;
-    const uint32_t j = it - base[k];
-    if (fd.dtype == 0)
-      cp_quad<float>(fd, j);
-    else
-      cp_quad<double>(fd, j);
+    const uint32_t q0 = (it - base[k]) * CP_ITEM_QUADS;
+    const uint32_t nq = min(((uint32_t)fd.K - 1 + 3) / 4, q0 + CP_ITEM_QUADS);
+    for (uint32_t j = q0 + threadIdx.x; j < nq; j += 256) {
+      if (fd.dtype == 0)
+        cp_quad<float>(fd, j);
+      else
+        cp_quad<double>(fd, j);
+    }
   }
 }
 
@@ -279,9 +284,12 @@ static void build_lists(const std::vector<const FieldDev *> &fds, const std::vec
   }
 }
 
-// Items of the critical-point compare of one field: four pairs each.
+// Items of the critical-point compare of one field: CP_ITEM_QUADS quads of
+// four pairs each.
 static uint32_t cp_items(const FieldDev &fd) {
-  return fd.K > 1 ? (uint32_t)((fd.K - 1 + 3) / 4) : 0u;
+  if (fd.K <= 1) return 0u;
+  const uint32_t nq = ((uint32_t)fd.K - 1 + 3) / 4;
+  return (nq + CP_ITEM_QUADS - 1) / CP_ITEM_QUADS;
 }
 
 // Items of the apply pass of one field: 4 * APPLY_ITEM_QUADS vertices each.
@@ -321,7 +329,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   }
   const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_boxes, 256 * 8));
   const int grid_apply = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_apply, 256 * 16));
-  const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>((max_cp + 255) / 256, 256 * 8));
+  const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_cp, 256 * 8));
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   hipGraphExec_t exec = nullptr;
   int exec_chunk = 0;
@@ -718,7 +726,7 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   HIP_OR_FAIL_B(hipEventRecord(ctx->step_copied, s));
   BatchShape shape;  // jobs use the default boxes (3D 4 x 4, 2D 16 x 1)
   const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(boxes, 256 * 8));
-  const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>((cps + 255) / 256, 256 * 8));
+  const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>(cps, 256 * 8));
   const int grid_apply = (int)std::max<uint64_t>(1, std::min<uint64_t>(words, 256 * 16));
   issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, grid_cp, (int)nf, grid_apply, s);
   HIP_OR_FAIL_B(hipGetLastError());
