@@ -131,7 +131,14 @@ exz_status exz_ctx_destroy(exz_ctx *ctx);
  *              > 0 that many (persistent);
  *   "frontier" 0/1: after the first pass, re-check only boxes in which the
  *              last apply changed a value or count (reformulated mode;
- *              default 1).
+ *              default 1);
+ *   "fused"    0/1: one kernel per pass applies the previous pass's edits
+ *              while it stages its box and checks it (reformulated mode, box
+ *              sides of at least two cells on every axis with more than one
+ *              box; otherwise ignored).  Same results; default 0, since the
+ *              separate check and apply kernels are faster on gfx950.  It
+ *              adds a second copy of g', counts, marks and dirty flags to
+ *              the workspace.
  * Returns EXZ_E_INVALID for an unknown key or value. */
 exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value);
 

@@ -457,6 +457,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     m.fd.tiles_y = (m.fd.ny + m.fd.tile_y - 1) / m.fd.tile_y;
     m.fd.tiles_z = (m.fd.nz + m.fd.tile_z - 1) / m.fd.tile_z;
     m.fd.ntiles = m.fd.tiles_x * m.fd.tiles_y * m.fd.tiles_z;
+    m.fd.fused = 0;  // batched iterations use separate check and apply launches
     m.fd.f = fl.f;
     m.fd.g_hat = fl.g_hat;
     m.fd.g = fl.g_out;
@@ -667,6 +668,7 @@ exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, ex
     fd.tiles_y = (fd.ny + fd.tile_y - 1) / fd.tile_y;
     fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
     fd.ntiles = fd.tiles_x * fd.tiles_y * fd.tiles_z;
+    fd.fused = 0;  // jobs advance with the batched launches
     st = setup_field(ctx, fd, field->f, field->g_hat, field->g_out, field->cnt_io,
                      field->params.max_iters, job->A, job->B, (hipStream_t)stream);
   }

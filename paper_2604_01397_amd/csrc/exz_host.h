@@ -59,12 +59,14 @@ struct exz_ctx {
   int tile_z = 0;
   int grid_blocks = -1;
   bool frontier = true;
+  bool fused = false;  // separate check and apply kernels are faster on gfx950
   std::string last_error;
   uint8_t *d_comp = nullptr;        // link component table (2^14 bytes)
   uint32_t *d_conn = nullptr;       // one-component bits (2^14 bits)
   exz::State *h_state = nullptr;    // pinned
   uint32_t *h_k = nullptr;          // pinned
   exz::Arena A, B, C;
+  exz::Arena F;  // second field / count buffers and rotating marks of fused passes
   exz::Arena BA, BB;  // batched correction workspaces
   void *step_host = nullptr;  // exz_step staging: pinned FieldDev array + item lists
   void *step_dev = nullptr;

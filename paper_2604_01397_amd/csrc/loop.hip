@@ -1,29 +1,31 @@
 // One iteration of the correction loop (Algorithm 1) on the device:
-//   check     CheckConstraints on every vertex (Sec. 4.2): steepest ascent and
-//             descent neighbours of g against f, link order of saddles
-//             (and of regular vertices of f that g turned into saddles).
-//             Each vertex writes the set of vertices it asks to decrease as
-//             a 15-bit slot mask (its neighbours and itself);
+//   check     CheckConstraints (Sec. 4.2): steepest ascent and descent
+//             neighbours of g against f, link order of saddles (and of
+//             regular vertices of f that g turned into saddles).  Each
+//             vertex marks the vertices it asks to decrease (its neighbours
+//             or itself) in a byte per vertex, the target set S;
 //   cpcmp     reformulated event constraints (Sec. 4.3): each critical point
 //             of f against its successor in f's sorted order; an inverted
-//             pair sets the request bit of the lower one on itself;
-//   apply     ApplyBoundedEdits (Sec. 3.3): a vertex is a target when it or
-//             a neighbour requested it; targets are edited in place;
+//             pair marks the lower one;
+//   apply     ApplyBoundedEdits (Sec. 3.3): every marked vertex is edited in
+//             place and its mark cleared;
 //   finalize  convergence / stuck / iteration-cap decision, counter reset.
-// The set S of Algorithm 1 is never materialised as a list: requests are
-// gathered (pulled) by their target, so no two threads write the same word
-// and no atomics are needed per target.  All checks of an iteration read the
-// same g, and the edits run in a later launch (synchronous, Jacobi-style
-// rounds).  Every kernel returns at once when the field is already done, so
-// a host may issue more iterations than needed and poll rarely.
+// A mark is a plain store of 1: many checks may mark the same vertex, and
+// every such store leaves the same byte, so no atomics are needed.  All
+// checks of an iteration read the same g, and the edits run in a later
+// launch (synchronous, Jacobi-style rounds).  Every kernel returns at once
+// when the field is already done, so a host may issue more iterations than
+// needed and poll rarely.
 //
-// check and apply are stencils over the 14-neighbour Freudenthal mesh.  A
-// work-group owns a 64 x TY x TZ box of vertices; every thread first issues
-// all of its loads of the box plus a one-cell halo (coalesced 66-wide rows)
-// into registers, then stores them to LDS, so many loads are in flight per
-// thread (the kernels are bound by HBM latency x parallelism otherwise), and
+// check is a stencil over the 14-neighbour Freudenthal mesh.  A work-group
+// owns a 64 x TY x TZ box of vertices; it stages the box plus a one-cell
+// halo row by row (coalesced loads, many in flight per thread) into LDS, and
 // each thread evaluates TZ vertices of one (x, y) column from LDS.  Halo
-// re-reads are served by L2: consecutive boxes run on the same XCD.
+// re-reads are served by L2: consecutive boxes run on the same XCD.  With
+// frontier passes, apply flags the boxes whose values or counts it changed
+// (and their neighbours), and the next check visits only flagged boxes; a
+// pass that changes nothing is followed by one dense pass before the loop
+// may stop, so the decision always rests on a check of every vertex.
 #include <algorithm>
 
 #include "loop_box.h"
@@ -134,6 +136,7 @@ __global__ void __launch_bounds__(64) k_state_reset(State *st, int64_t max_iters
   st->cert_bad = 0;
   st->nsaddle = 0;
   st->dense = 1;
+  st->prev_dense = 0;
   st->iterations = st->edit_ops = st->lossless_total = st->floor_total = st->edited_total = 0;
   st->residual = 0;
   st->max_iters = max_iters;
@@ -191,6 +194,22 @@ static void launch_phases(const FieldDev &fd, const uint32_t *conn, const uint8_
   launch_check_cpcmp<T>(fd, conn, comp, s, ev0, ev1);
   launch_apply<T>(fd, s);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, fd);
+}
+
+hipError_t launch_cpcmp_only(const FieldDev &fd, hipStream_t s) {
+  if (fd.K > 1) {
+    const dim3 grid((fd.K - 1 + 4 * CP_BLOCK - 1) / (4 * CP_BLOCK));
+    if (fd.dtype == 0)
+      hipLaunchKernelGGL(k_cpcmp<float>, grid, dim3(CP_BLOCK), 0, s, fd);
+    else
+      hipLaunchKernelGGL(k_cpcmp<double>, grid, dim3(CP_BLOCK), 0, s, fd);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FieldDev &fd, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, fd);
+  return hipGetLastError();
 }
 
 hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,

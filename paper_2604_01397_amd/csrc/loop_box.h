@@ -251,11 +251,19 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__
 // Reformulated event constraints: consecutive critical points in f's order
 // must keep their order in g; an inverted pair decreases the lower one.
 // Values are finite, so b > a settles most pairs without the vertex indices.
+__device__ __forceinline__ void mark_box_range(const FieldDev &fd, uint32_t x0, uint32_t x1,
+                                               uint32_t y, uint32_t z);
+
 template <class T>
 __device__ __forceinline__ void cp_pair_vals(const FieldDev &fd, uint32_t r, T a, T b) {
   if (b > a) return;
   const uint32_t ia = glob(fd.cp_idx)[r], ib = glob(fd.cp_idx)[r + 1];
-  if (sos_lt(b, ib, a, ia)) mark_target(fd.tmark, ia);
+  if (!sos_lt(b, ib, a, ia)) return;
+  mark_target(fd.tmark, ia);
+  if (fd.fused && fd.frontier) {  // the boxes whose check reads the target
+    const uint32_t x = ia % (uint32_t)fd.nx, q = ia / (uint32_t)fd.nx;
+    mark_box_range(fd, x, x, q % (uint32_t)fd.ny, q / (uint32_t)fd.ny);
+  }
 }
 
 template <class T>
@@ -464,7 +472,8 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
   State *st = fd.st;
   if (st->done) return;
   const int lane = threadIdx.x;
-  if (lane == 0) st->passes += 1;
+  const int64_t pass = st->passes;  // passes before this one
+  if (lane == 0) st->passes = pass + 1;
   uint32_t v[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -473,14 +482,23 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
   }
   if (lane != 0) return;
   const uint32_t nt = v[0], ch = v[1];
+  if (fd.fused && pass == 0) {  // a fused first pass only checks: nothing applied yet
+    st->prev_dense = st->dense;
+    st->dense = 0;
+    return;
+  }
   if (fd.trace && st->iterations < fd.trace_cap) {
     fd.trace[2 * st->iterations] = nt;
     fd.trace[2 * st->iterations + 1] = ch;
   }
-  if (ch == 0 && fd.frontier && !st->dense) {
+  // Were the targets just applied named by a check that covered every box?
+  // (A fused pass applies the targets of the previous pass's check.)
+  const bool complete = fd.fused ? st->prev_dense != 0 : st->dense != 0;
+  if (fd.fused) st->prev_dense = st->dense;
+  if (ch == 0 && fd.frontier && !complete) {
     // A frontier pass skips boxes whose requests were all blocked, so it
-    // cannot tell a fixpoint from convergence (or count the residual): one
-    // dense pass over the unchanged field settles it.
+    // cannot tell a fixpoint from convergence (or count the residual): dense
+    // passes over the unchanged field settle it.
     st->dense = 1;
   } else if (nt == 0) {
     st->done = CONVERGED;
