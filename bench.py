@@ -174,8 +174,6 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time every compiled box shape first")
     ap.add_argument("--grid", type=int, default=-1, help="stencil grid (-1 persistent, 0 per box)")
     ap.add_argument("--frontier", type=int, default=1, help="1: frontier check passes (default)")
-    ap.add_argument("--fused", type=int, default=0,
-                    help="1: apply and check in one kernel per pass (0: separate kernels, default)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and serving measurements")
     ap.add_argument("--serve-jobs", type=int, default=200, help="jobs in the serving trace")
@@ -213,23 +211,20 @@ def main():
     g_out = torch.empty_like(f)
     cnt = torch.zeros(f.shape, dtype=torch.uint8, device=dev)
     ctx = exactz.Context(0, profile=1, poll=args.poll, tile=args.tile, grid=args.grid,
-                         frontier=args.frontier, fused=args.fused)
+                         frontier=args.frontier)
     if args.sweep:
-        for fr in (0, 1):
-            ctx.set_option("fused", fr)
-            for grid in (-1, 0):
-                ctx.set_option("grid", grid)
-                for shape in (202, 402, 404, 802, 804, 408, 1602):
-                    ctx.set_option("tile", shape)
-                    ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt, max_iters=2)
-                    _, _, r = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt)
-                    log("fused %d grid %2d tile %4d: check %.4f ms/launch (%d launches, "
-                        "%.3g vertices), loop %.2f ms, setup %.2f ms" % (
-                            fr, grid, shape, r["check_ms"] / max(r["check_launches"], 1),
-                            r["check_launches"], r["check_vertices"], r["loop_ms"], r["setup_ms"]))
+        for grid in (-1, 0):
+            ctx.set_option("grid", grid)
+            for shape in (202, 402, 404, 802, 804, 408, 1602):
+                ctx.set_option("tile", shape)
+                ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt, max_iters=2)
+                _, _, r = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt)
+                log("grid %2d tile %4d: check %.4f ms/launch (%d launches, "
+                    "%.3g vertices), loop %.2f ms, setup %.2f ms" % (
+                        grid, shape, r["check_ms"] / max(r["check_launches"], 1),
+                        r["check_launches"], r["check_vertices"], r["loop_ms"], r["setup_ms"]))
         ctx.set_option("tile", args.tile)
         ctx.set_option("grid", args.grid)
-        ctx.set_option("fused", args.fused)
     stream = torch.cuda.current_stream()
     res = None
     for w in range(args.warmup):

@@ -129,16 +129,11 @@ exz_status exz_ctx_destroy(exz_ctx *ctx);
  *              "tile_z" set one side;
  *   "grid"     check work-groups: -1 persistent (default), 0 one per box,
  *              > 0 that many (persistent);
- *   "frontier" 0/1: after the first pass, re-check only boxes in which the
- *              last apply changed a value or count (reformulated mode;
- *              default 1);
- *   "fused"    0/1: one kernel per pass applies the previous pass's edits
- *              while it stages its box and checks it (reformulated mode, box
- *              sides of at least two cells on every axis with more than one
- *              box; otherwise ignored).  Same results; default 0, since the
- *              separate check and apply kernels are faster on gfx950.  It
- *              adds a second copy of g', counts, marks and dirty flags to
- *              the workspace.
+ *   "frontier" 0/1: after the first pass, re-check only boxes whose check
+ *              reads a value the last apply changed: a vertex of the box or
+ *              its halo, or the successor in f's order of one of its
+ *              critical points (reformulated mode; default 1).  A pass that
+ *              changes nothing is followed by a check of every box.
  * Returns EXZ_E_INVALID for an unknown key or value. */
 exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value);
 

@@ -153,11 +153,6 @@ exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd) {
   // original mode rewrites g's pointer labels by pointer jumping every
   // iteration, so its check pass always covers every box
   fd.frontier = (ctx ? ctx->frontier : true) && p->event_mode == EXZ_EVENT_REFORMULATED;
-  // fused passes mark the next pass's boxes by per-axis neighbour masks,
-  // which need boxes at least two cells deep on every axis with more than one
-  // box row
-  fd.fused = (ctx ? ctx->fused : false) && p->event_mode == EXZ_EVENT_REFORMULATED &&
-             !(fd.tile_y == 1 && fd.ny > 1) && !(fd.tile_z == 1 && fd.nz > 1);
   const int nxy = fd.nx * fd.ny;
   for (int s = 0; s < NSLOT; ++s) fd.dlt[s] = DXS[s] + fd.nx * DYS[s] + nxy * DZS[s];
   fd.dlt[SELF] = 0;
@@ -187,13 +182,13 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
   off[1] = L.add(3 * n);                                     // code, low
   off[2] = L.add(8 * (size_t)fd.nchunk);                     // cpbits
   off[3] = L.add(4 * ((size_t)fd.nchunk + 1));               // cpoff
-  off[4] = L.add(16 * (size_t)fused_mark_words(fd));  // target marks + zero padding
-  off[5] = L.add(4 * n);                                     // rank_of
+  off[4] = L.add(mark_bytes(fd));                            // target marks + zero padding
+  off[5] = L.add(8 * n);                                     // succ, pred_box
   off[6] = own_cnt ? L.add(n) : 0;                           // cnt
   off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
   // dirty box flags, sized for the smallest box (64 x 1 x 1) so the
   // footprint does not depend on the box shape
-  off[8] = L.add((size_t)fd.tiles_x * (size_t)fd.ny * (size_t)fd.nz);
+  off[8] = L.add(box_flag_bytes(fd));
   (void)trace_cap;
   (void)need_lab;
 }
@@ -207,7 +202,7 @@ void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]) {
   off[1] = L.add(4 * (size_t)Kc);  // cp_vtx
   off[2] = 0;
   off[3] = L.add(4 * (size_t)Kc);  // cp_idx
-  off[4] = L.add(b * Kc);          // cp_val
+  off[4] = 0;
   off[5] = L.add(kb * Kc);         // keys
   off[6] = L.add(kb * Kc);         // keys tmp
   off[7] = L.add(4 * (size_t)Kc);  // vals
@@ -237,7 +232,8 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   fd.cpoff = (uint32_t *)(base + oa[3]);
   fd.tmark = (uint8_t *)(base + oa[4]);
   fd.bdirty = (uint8_t *)(base + oa[8]);
-  fd.rank_of = (uint32_t *)(base + oa[5]);
+  fd.succ = (uint32_t *)(base + oa[5]);
+  fd.pred_box = fd.succ + fd.n;
   fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
   fd.vec = quad_aligned(fd);
   uint32_t *scan_tmp = (uint32_t *)(base + oa[7]);
@@ -262,7 +258,6 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   char *bb = (char *)B.take(LB.total);
   fd.cp_vtx = (uint32_t *)(bb + ob[1]);
   fd.cp_idx = (uint32_t *)(bb + ob[3]);
-  fd.cp_val = bb + ob[4];
   void *keys = bb + ob[5];
   void *keys_tmp = bb + ob[6];
   uint32_t *vals = (uint32_t *)(bb + ob[7]);
@@ -369,7 +364,6 @@ exz_status exz_ctx_destroy(exz_ctx *ctx) {
   ctx->A.release();
   ctx->B.release();
   ctx->C.release();
-  ctx->F.release();
   ctx->BA.release();
   ctx->BB.release();
   if (ctx->step_host) (void)hipHostFree(ctx->step_host);
@@ -416,8 +410,6 @@ exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value) {
     ctx->tile_z = tz;
   } else if (k == "frontier") {  // 1: re-check only changed boxes (reformulated mode)
     ctx->frontier = value != 0;
-  } else if (k == "fused") {  // 1: apply and check in one pass (reformulated mode)
-    ctx->fused = value != 0;
   } else if (k == "grid") {  // stencil work-groups: -1 persistent (default), 0 one per box
     if (value < -1 || value > (1 << 24)) return fail(ctx, EXZ_E_INVALID, "grid must be -1..2^24");
     ctx->grid_blocks = (int)value;
@@ -444,13 +436,7 @@ size_t exz_workspace_bytes(const exz_params *p) {
   size_t oc[6];
   fd.K = fd.n;
   layout_c(fd, p->event_mode == EXZ_EVENT_ORIGINAL, p->certify != 0, LC, oc);
-  size_t fused = 0;
-  if (fd.fused) {  // second field and count buffers, two mark buffers, dirty flags
-    const size_t n = (size_t)fd.n, b = p->dtype == EXZ_F32 ? 4 : 8;
-    fused = n * b + n + 2 * 16 * (size_t)fused_mark_words(fd) +
-            (size_t)fd.tiles_x * (size_t)fd.ny * (size_t)fd.nz + 5 * 256;
-  }
-  return LA.total + LB.total + LC.total + fused;
+  return LA.total + LB.total + LC.total;
 }
 
 static void fill_result(exz_result *r, const State &st, int status) {
@@ -551,31 +537,6 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   st = setup_paths(ctx, fd, params->event_mode == EXZ_EVENT_ORIGINAL, params->certify != 0,
                    ctx->C, &lab_g, s);
   if (st != EXZ_OK) return st;
-  // Fused passes: a second field and count buffer, two more mark buffers and
-  // a second set of dirty flags (the first of each comes from phase A).
-  FusedBufs fb = {};
-  if (fd.fused) {
-    const size_t n = (size_t)fd.n, b = fd.dtype == 0 ? 4 : 8;
-    const size_t mb = 16 * (size_t)fused_mark_words(fd);
-    const size_t db = (size_t)fd.tiles_x * (size_t)fd.ny * (size_t)fd.nz;
-    Layout LF;
-    const size_t og = LF.add(n * b), oc = LF.add(n + 16), om1 = LF.add(mb), om2 = LF.add(mb),
-                 od = LF.add(db);
-    HIP_OR_FAIL(ctx->F.reserve(LF.total));
-    char *fbase = (char *)ctx->F.take(LF.total);
-    fb.g[0] = fd.g;
-    fb.g[1] = fbase + og;
-    fb.cnt[0] = fd.cnt;
-    fb.cnt[1] = (uint8_t *)(fbase + oc);
-    fb.marks[0] = fd.tmark;  // cleared by the set-up
-    fb.marks[1] = (uint8_t *)(fbase + om1);
-    fb.marks[2] = (uint8_t *)(fbase + om2);
-    fb.dirty[0] = fd.bdirty;  // cleared by the set-up
-    fb.dirty[1] = (uint8_t *)(fbase + od);
-    HIP_OR_FAIL(hipMemsetAsync(fb.marks[1], 0, mb, s));
-    HIP_OR_FAIL(hipMemsetAsync(fb.marks[2], 0, mb, s));
-    HIP_OR_FAIL(hipMemsetAsync(fb.dirty[1], 0, db, s));
-  }
   HIP_OR_FAIL(hipEventRecord(ctx->ev_setup, s));
 
   // Iterations are issued in chunks; each chunk ends with an asynchronous
@@ -584,8 +545,8 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   // GPU never waits for the host; after convergence the kernels return at
   // once, so the chunk issued past the end costs only its launches.
   // every changing iteration moves a value down and a vertex moves at most
-  // N + 1 times; at most four more passes (fused first pass, the pass that
-  // finds the fixpoint and two confirming ones) change nothing
+  // N + 1 times; at most two more passes (the frontier pass that finds the
+  // fixpoint and the dense one that confirms it) change nothing
   const int64_t cap = (int64_t)(fd.N + 1) * fd.n + 4;
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   int64_t issued = 0;
@@ -607,10 +568,7 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
         e1 = ctx->events[ev_used + 1];
         ev_used += 2;
       }
-      if (fd.fused)
-        HIP_OR_FAIL(launch_fused_pass(fd, fb, issued + k, ctx->d_conn, ctx->d_comp, s, e0, e1));
-      else
-        HIP_OR_FAIL(launch_iteration(fd, ctx->d_conn, ctx->d_comp, s, e0, e1));
+      HIP_OR_FAIL(launch_iteration(fd, ctx->d_conn, ctx->d_comp, s, e0, e1));
     }
     issued += chunk;
     HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state + slot, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
@@ -632,12 +590,6 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   // the chunk still in flight ran past the fixpoint; its copy holds the final state
   HIP_OR_FAIL(hipEventSynchronize(ctx->poll_ev[1 - slot]));
   ctx->h_state[0] = ctx->h_state[1 - slot];
-  if (fd.fused && (ctx->h_state[0].passes & 1)) {
-    // after an odd number of fused passes the result is in the second buffer
-    const size_t n = (size_t)fd.n, b = fd.dtype == 0 ? 4 : 8;
-    HIP_OR_FAIL(hipMemcpyAsync(fd.g, fb.g[1], n * b, hipMemcpyDeviceToDevice, s));
-    HIP_OR_FAIL(hipMemcpyAsync(fd.cnt, fb.cnt[1], n, hipMemcpyDeviceToDevice, s));
-  }
   if (params->certify) {
     HIP_OR_FAIL(launch_certify(fd, ctx->d_comp, lab_g, s));
     HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));

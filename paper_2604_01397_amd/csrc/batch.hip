@@ -4,9 +4,9 @@
 // set, own critical-point order, own convergence flag and counters); what is
 // shared is the launch.  One iteration over the whole batch is four launches
 // of persistent kernels that walk a device-resident list of work items:
-//   check   (field, box) items of every unconverged field,
-//   cpcmp   (field, critical-point pair) items,
-//   apply   (field, box) items,
+//   check   (field, box) items of every unconverged field (one launch per
+//           value type and dimensionality),
+//   apply   (field, vertex range) items,
 //   finalize one wave per field.
 // Items are laid out field after field with a prefix array, so a block finds
 // its field by binary search; blocks of converged fields never get items
@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(64 * TY)
     k_check_batch(const FieldDev *__restrict__ fields, const uint32_t *__restrict__ lists,
                   const uint32_t *__restrict__ conn) {
   __shared__ CheckLds<T, TY, TZ> L;
+  load_conn(L, conn);
   const uint32_t nf = lists[0], total = lists[1];
   const uint32_t *field = lists + 2, *base = lists + 2 + nf;
   uint32_t k = 0;
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(64 * TY)
         __syncthreads();  // every thread has read the flag
         if (threadIdx.x == 0 && threadIdx.y == 0) fd.bdirty[tile] = 0;
       }
-      check_box<T, TY, TZ>(fd, conn, box_of(fd, tile, TY, TZ), L);
+      check_box<T, TY, TZ>(fd, box_of(fd, tile, TY, TZ), L);
     }
     __syncthreads();
   }
@@ -108,30 +109,6 @@ __global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *__r
     }
   }
   if (nf) flush_counts<APPLY_BLOCK / 64>(fields[field[kc]].st, ec, blockIdx.x);
-}
-
-// Critical-point pairs in quads of four; one item is CP_ITEM_QUADS quads
-// of one field (field k owns items [base[k], base[k+1])).
-constexpr uint32_t CP_ITEM_QUADS = 4 * 256;
-
-__global__ void __launch_bounds__(256) k_cpcmp_batch(const FieldDev *__restrict__ fields,
-                                                     const uint32_t *__restrict__ lists) {
-  const uint32_t nf = lists[0], total = lists[1];
-  const uint32_t *field = lists + 2, *base = lists + 2 + nf;
-  uint32_t k = 0;
-  for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
-    k = next_field_uniform(base, nf, it, k);
-    const FieldDev &fd = fields[__builtin_amdgcn_readfirstlane(field[k])];
-    if (fd.st->done) continue;
-    const uint32_t q0 = (it - base[k]) * CP_ITEM_QUADS;
-    const uint32_t nq = min(((uint32_t)fd.K - 1 + 3) / 4, q0 + CP_ITEM_QUADS);
-    for (uint32_t j = q0 + threadIdx.x; j < nq; j += 256) {
-      if (fd.dtype == 0)
-        cp_quad<float>(fd, j);
-      else
-        cp_quad<double>(fd, j);
-    }
-  }
 }
 
 __global__ void __launch_bounds__(64) k_finalize_batch(const FieldDev *fields, const uint32_t *lists) {
@@ -218,9 +195,9 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
 }  // namespace exz
 
 // Device list buffers, capacity per list 2 + 2*nf + 1 words: boxes of 3D
-// float32 / 3D float64 / 2D-1D float32 / 2D-1D float64 fields, critical-point
-// quads, finalize (one item per field), apply chunks.
-enum { L_BOX3F, L_BOX3D, L_BOX2F, L_BOX2D, L_CP, L_FIN, L_APPLY, NLISTS };
+// float32 / 3D float64 / 2D-1D float32 / 2D-1D float64 fields, finalize (one
+// item per field), apply chunks.
+enum { L_BOX3F, L_BOX3D, L_BOX2F, L_BOX2D, L_FIN, L_APPLY, NLISTS };
 static size_t list_words(size_t nf) { return 2 + 2 * nf + 1; }
 
 namespace exz {
@@ -238,22 +215,20 @@ static void box_launch_check(int ty, int tz, const FieldDev *fields, const uint3
 
 // Issue `iters` batched iterations.
 static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dlists, size_t lw,
-                             const BatchShape &shape, int iters, int grid_box, int grid_cp,
+                             const BatchShape &shape, int iters, int grid_box,
                              int grid_fin, int grid_apply, hipStream_t s) {
   auto list = [&](int q) { return dlists + q * lw; };
-  uint32_t *lc = list(L_CP), *lf = list(L_FIN), *la = list(L_APPLY);
+  uint32_t *lf = list(L_FIN), *la = list(L_APPLY);
   for (int it = 0; it < iters; ++it) {
     box_launch_check<float>(shape.ty3, shape.tz3, fields, list(L_BOX3F), ctx->d_conn, grid_box, s);
     box_launch_check<double>(shape.ty3, shape.tz3, fields, list(L_BOX3D), ctx->d_conn, grid_box, s);
     box_launch_check<float>(shape.ty2, shape.tz2, fields, list(L_BOX2F), ctx->d_conn, grid_box, s);
     box_launch_check<double>(shape.ty2, shape.tz2, fields, list(L_BOX2D), ctx->d_conn, grid_box, s);
-    hipLaunchKernelGGL(k_cpcmp_batch, dim3(grid_cp), dim3(256), 0, s, fields, lc);
     hipLaunchKernelGGL(k_apply_batch, dim3(grid_apply), dim3(APPLY_BLOCK), 0, s, fields, la);
     hipLaunchKernelGGL(k_finalize_batch, dim3(grid_fin), dim3(64), 0, s, fields, lf);
   }
 }
 
-static uint32_t cp_items(const FieldDev &fd);
 static uint32_t apply_items(const FieldDev &fd);
 
 // Host item lists of one batched iteration over the fields fds[k] with
@@ -270,8 +245,6 @@ static void build_lists(const std::vector<const FieldDev *> &fds, const std::vec
                               : (fd.dtype == 0 ? L_BOX2F : L_BOX2D);
     f[box].push_back(idx);
     n[box].push_back((uint32_t)fd.ntiles);
-    f[L_CP].push_back(idx);
-    n[L_CP].push_back(cp_items(fd));
     f[L_FIN].push_back(idx);
     n[L_FIN].push_back(1);
     f[L_APPLY].push_back(idx);
@@ -282,14 +255,6 @@ static void build_lists(const std::vector<const FieldDev *> &fds, const std::vec
     L.build(f[q], n[q]);
     std::memcpy(hl + q * lw, L.v.data(), L.v.size() * 4);
   }
-}
-
-// Items of the critical-point compare of one field: CP_ITEM_QUADS quads of
-// four pairs each.
-static uint32_t cp_items(const FieldDev &fd) {
-  if (fd.K <= 1) return 0u;
-  const uint32_t nq = ((uint32_t)fd.K - 1 + 3) / 4;
-  return (nq + CP_ITEM_QUADS - 1) / CP_ITEM_QUADS;
 }
 
 // Items of the apply pass of one field: 4 * APPLY_ITEM_QUADS vertices each.
@@ -321,15 +286,13 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   HIP_OR_FAIL_B(hipHostMalloc((void **)&hstates, std::max<size_t>(nf, 1) * sizeof(State),
                               hipHostMallocDefault));
   // persistent grids: enough blocks to fill the chip, never more than items
-  uint64_t max_boxes = 0, max_cp = 0, max_apply = 0;
+  uint64_t max_boxes = 0, max_apply = 0;
   for (auto &m : members) {
     max_boxes += (uint64_t)m.fd.ntiles;
-    max_cp += cp_items(m.fd);
     max_apply += apply_items(m.fd);
   }
   const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_boxes, 256 * 8));
   const int grid_apply = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_apply, 256 * 16));
-  const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_cp, 256 * 8));
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   hipGraphExec_t exec = nullptr;
   int exec_chunk = 0;
@@ -354,7 +317,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
         exec = nullptr;
         hipGraph_t graph = nullptr;
         HIP_OR_FAIL_B(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_cp, grid_fin,
+        issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_fin,
                          grid_apply, s);
         const hipError_t ce = hipStreamEndCapture(s, &graph);  // always ends the capture
         HIP_OR_FAIL_B(ce);
@@ -365,7 +328,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
       }
       HIP_OR_FAIL_B(hipGraphLaunch(exec, s));
     } else {
-      issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_cp, grid_fin,
+      issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_fin,
                          grid_apply, s);
       HIP_OR_FAIL_B(hipGetLastError());
     }
@@ -457,7 +420,6 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     m.fd.tiles_y = (m.fd.ny + m.fd.tile_y - 1) / m.fd.tile_y;
     m.fd.tiles_z = (m.fd.nz + m.fd.tile_z - 1) / m.fd.tile_z;
     m.fd.ntiles = m.fd.tiles_x * m.fd.tiles_y * m.fd.tiles_z;
-    m.fd.fused = 0;  // batched iterations use separate check and apply launches
     m.fd.f = fl.f;
     m.fd.g_hat = fl.g_hat;
     m.fd.g = fl.g_out;
@@ -500,7 +462,8 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.cpoff = (uint32_t *)(b + oa[k][3]);
       fd.tmark = (uint8_t *)(b + oa[k][4]);
       fd.bdirty = (uint8_t *)(b + oa[k][8]);
-      fd.rank_of = (uint32_t *)(b + oa[k][5]);
+      fd.succ = (uint32_t *)(b + oa[k][5]);
+      fd.pred_box = fd.succ + fd.n;
       uint8_t *cnt_io = fields[mem[k].index].cnt_io;
       fd.cnt = cnt_io ? cnt_io : (uint8_t *)(b + oa[k][6]);
       fd.vec = quad_aligned(fd);
@@ -552,7 +515,6 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       char *b = Bm + baseB[k];
       fd.cp_vtx = (uint32_t *)(b + ob[k][1]);
       fd.cp_idx = (uint32_t *)(b + ob[k][3]);
-      fd.cp_val = b + ob[k][4];
       const uint32_t K = (uint32_t)fd.K;
       if (K > 0) {
         const size_t hw = radix_hist_words(K);
@@ -668,7 +630,6 @@ exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, ex
     fd.tiles_y = (fd.ny + fd.tile_y - 1) / fd.tile_y;
     fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
     fd.ntiles = fd.tiles_x * fd.tiles_y * fd.tiles_z;
-    fd.fused = 0;  // jobs advance with the batched launches
     st = setup_field(ctx, fd, field->f, field->g_hat, field->g_out, field->cnt_io,
                      field->params.max_iters, job->A, job->B, (hipStream_t)stream);
   }
@@ -708,7 +669,7 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   }
   FieldDev *hf = (FieldDev *)ctx->step_host;
   uint32_t *hl = (uint32_t *)(hf + nf);
-  uint64_t boxes = 0, cps = 0, words = 0;
+  uint64_t boxes = 0, words = 0;
   std::vector<const FieldDev *> fds(nf);
   std::vector<bool> act(nf, true);
   for (size_t k = 0; k < nf; ++k) {
@@ -718,7 +679,6 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
     fds[k] = &hf[k];
     words += apply_items(fd);
     boxes += (uint64_t)fd.ntiles;
-    cps += cp_items(fd);
     jobs[k]->last = s;
   }
   build_lists(fds, act, hl, lw);
@@ -726,11 +686,10 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   uint32_t *dl = (uint32_t *)(df + nf);
   HIP_OR_FAIL_B(hipMemcpyAsync(df, hf, bytes, hipMemcpyHostToDevice, s));
   HIP_OR_FAIL_B(hipEventRecord(ctx->step_copied, s));
-  BatchShape shape;  // jobs use the default boxes (3D 4 x 4, 2D 16 x 1)
+  BatchShape shape;  // jobs use the default boxes (3D 4 x 8, 2D 16 x 1)
   const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(boxes, 256 * 8));
-  const int grid_cp = (int)std::max<uint64_t>(1, std::min<uint64_t>(cps, 256 * 8));
   const int grid_apply = (int)std::max<uint64_t>(1, std::min<uint64_t>(words, 256 * 16));
-  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, grid_cp, (int)nf, grid_apply, s);
+  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, (int)nf, grid_apply, s);
   HIP_OR_FAIL_B(hipGetLastError());
   return EXZ_OK;
 }

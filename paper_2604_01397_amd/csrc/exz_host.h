@@ -38,6 +38,15 @@ inline int quad_aligned(const FieldDev &fd) {
   return ((uintptr_t)fd.f % 16 == 0) && ((uintptr_t)fd.g % 16 == 0) && ((uintptr_t)fd.cnt % 4 == 0);
 }
 
+// Bytes of the target marks: one per vertex, then zero padding (apply reads
+// marks four at a time), rounded to 16.
+inline size_t mark_bytes(const exz::FieldDev &fd) { return ((size_t)fd.n + 64 + 15) / 16 * 16; }
+
+// Bytes of the dirty-box flags: one per box of the smallest shape.
+inline size_t box_flag_bytes(const exz::FieldDev &fd) {
+  return (size_t)fd.tiles_x * (size_t)fd.ny * (size_t)fd.nz;
+}
+
 void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, Layout &L,
               size_t off[9]);
 void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]);
@@ -59,14 +68,12 @@ struct exz_ctx {
   int tile_z = 0;
   int grid_blocks = -1;
   bool frontier = true;
-  bool fused = false;  // separate check and apply kernels are faster on gfx950
   std::string last_error;
   uint8_t *d_comp = nullptr;        // link component table (2^14 bytes)
   uint32_t *d_conn = nullptr;       // one-component bits (2^14 bits)
   exz::State *h_state = nullptr;    // pinned
   uint32_t *h_k = nullptr;          // pinned
   exz::Arena A, B, C;
-  exz::Arena F;  // second field / count buffers and rotating marks of fused passes
   exz::Arena BA, BB;  // batched correction workspaces
   void *step_host = nullptr;  // exz_step staging: pinned FieldDev array + item lists
   void *step_dev = nullptr;

@@ -27,6 +27,7 @@ constexpr int DZS[NSLOT] = {0, 0, 0, 0, 0, 0, +1, -1, +1, -1, +1, -1, +1, -1};
 // Both are read with coalesced loads by the check pass.
 constexpr uint32_t LOW_SADDLE = 1u << 15;
 constexpr uint32_t LOW_MASK = 0x3FFFu;
+constexpr uint32_t NONE = 0xFFFFFFFFu;  // no vertex / no box
 
 enum Done : int32_t { RUNNING = 0, CONVERGED = 1, STUCK = 2, MAXITERS = 3 };
 constexpr int MAX_JUMP_ROUNDS = 34;  // pointer jumping over < 2^32 labels
@@ -46,7 +47,6 @@ struct State {
   uint32_t shard[5][64];  // per-iteration counters of the apply pass, sharded by block
   uint32_t nsaddle;       // saddles of f (original mode)
   int32_t dense;          // the next check covers every box (first pass, fixpoint confirmation)
-  int32_t prev_dense;     // fused passes: the last pass's check covered every box
   uint32_t jump[MAX_JUMP_ROUNDS];  // pointer-jumping round flags
   int64_t iterations;
   int64_t edit_ops;
@@ -78,7 +78,6 @@ struct FieldDev {
   int32_t frontier;     // 1: re-check only boxes whose closed neighbourhood changed
   int32_t ty_shift, tz_shift;  // log2 of tile_y / tile_z
   int32_t vec;          // f, g 16-byte and cnt 4-byte aligned: apply reads four vertices at once
-  int32_t fused;        // passes apply the previous pass's targets and check in one sweep
   int32_t dlt[16];      // linear index offset of each slot (dlt[SELF] = 0)
   double xiT, delta;    // in the field type, widened exactly to double
   const void *f;
@@ -90,27 +89,17 @@ struct FieldDev {
   unsigned long long *cpbits;
   uint32_t *cpoff;      // nchunk + 1 exclusive prefix counts
   uint32_t *cp_vtx;     // K, vertex order -> vertex
-  uint32_t *rank_of;    // n: rank of a critical point in the sorted CP order, ~0 otherwise
+  uint32_t *succ;       // n: the next critical point of f in f's order, NONE otherwise
+  uint32_t *pred_box;   // n: box holding the previous critical point of f, NONE otherwise
   uint32_t *cp_idx;     // K, rank -> vertex
-  void *cp_val;         // K, rank -> current g value
   uint32_t *sad_rank;   // saddle order -> rank in the CP order (K capacity)
   uint32_t *sel_f;      // 2 per saddle: selections in f (join, split) or ~0
   uint32_t *lab;        // 2n: g's descent / ascent labels (original mode)
   uint32_t *lab_f;      // 2n: f's resolved path termini (original mode, certificate)
   uint8_t *tmark;       // n: the target set of the iteration (1 = decrease this vertex)
-  uint8_t *bdirty;      // ntiles: boxes whose closed neighbourhood the last apply changed
+  uint8_t *bdirty;      // ntiles: boxes whose check reads a value the last apply changed
   int64_t *trace;       // 2 * trace_cap (|S|, changed) per iteration, nullable
   State *st;
-};
-
-// Rotating buffers of fused passes: field and counts (2 each: read / write),
-// target marks (3: previous pass / this pass / next pass, cleared), dirty
-// box flags (2: this pass / next pass).
-struct FusedBufs {
-  void *g[2];
-  uint8_t *cnt[2];
-  uint8_t *marks[3];
-  uint8_t *dirty[2];
 };
 
 // ---------------------------------------------------------------------------
@@ -279,11 +268,7 @@ bool box_supported(int tile_y, int tile_z);
 hipError_t launch_state_reset(const FieldDev &fd, int64_t max_iters, hipStream_t s);
 hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,
                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_cpcmp_only(const FieldDev &fd, hipStream_t s);
 hipError_t launch_finalize(const FieldDev &fd, hipStream_t s);
-hipError_t launch_fused_pass(FieldDev fd, const FusedBufs &fb, int64_t p, const uint32_t *conn,
-                             const uint8_t *comp, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
-uint32_t fused_mark_words(const FieldDev &fd);
 hipError_t launch_certify(const FieldDev &fd, const uint8_t *comp, uint32_t *lab_g, hipStream_t s);
 hipError_t launch_original_setup(const FieldDev &fd, const uint8_t *comp, uint32_t *tmp,
                                  uint32_t *scan_tmp, size_t scan_words, hipStream_t s);

@@ -1,12 +1,12 @@
 // One iteration of the correction loop (Algorithm 1) on the device:
 //   check     CheckConstraints (Sec. 4.2): steepest ascent and descent
 //             neighbours of g against f, link order of saddles (and of
-//             regular vertices of f that g turned into saddles).  Each
-//             vertex marks the vertices it asks to decrease (its neighbours
-//             or itself) in a byte per vertex, the target set S;
-//   cpcmp     reformulated event constraints (Sec. 4.3): each critical point
-//             of f against its successor in f's sorted order; an inverted
-//             pair marks the lower one;
+//             regular vertices of f that g turned into saddles), and the
+//             reformulated event constraints (Sec. 4.3): each critical point
+//             of f against the next one in f's order, whose value is
+//             gathered from g.  Each vertex marks the vertices it asks to
+//             decrease (its neighbours or itself) in a byte per vertex, the
+//             target set S;
 //   apply     ApplyBoundedEdits (Sec. 3.3): every marked vertex is edited in
 //             place and its mark cleared;
 //   finalize  convergence / stuck / iteration-cap decision, counter reset.
@@ -22,10 +22,12 @@
 // halo row by row (coalesced loads, many in flight per thread) into LDS, and
 // each thread evaluates TZ vertices of one (x, y) column from LDS.  Halo
 // re-reads are served by L2: consecutive boxes run on the same XCD.  With
-// frontier passes, apply flags the boxes whose values or counts it changed
-// (and their neighbours), and the next check visits only flagged boxes; a
-// pass that changes nothing is followed by one dense pass before the loop
-// may stop, so the decision always rests on a check of every vertex.
+// frontier passes, apply flags the boxes whose check reads a value it
+// changed: the boxes around the vertex, and the box of the previous critical
+// point in f's order, which compares itself with the vertex.  The next check
+// visits only flagged boxes; a pass that changes nothing is followed by one
+// dense pass before the loop may stop, so the decision always rests on a
+// check of every vertex.
 #include <algorithm>
 
 #include "loop_box.h"
@@ -60,13 +62,14 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   if (st->done) return;
   __shared__ CheckLds<T, TY, TZ> L;
   __shared__ unsigned long long pick;
+  load_conn(L, conn);
   const BoxWalk w = box_walk(fd);
   const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
   uint32_t done_v = 0;  // vertices checked by this work-group (lead thread)
   if (!fd.frontier || st->dense) {
     for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
       const BoxOrigin o = box_of(fd, tile, TY, TZ);
-      check_box<T, TY, TZ>(fd, conn, o, L);
+      check_box<T, TY, TZ>(fd, o, L);
       if (lead) done_v += box_vertices(fd, o, TY, TZ);
       __syncthreads();
     }
@@ -94,23 +97,13 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
         const uint32_t k = (uint32_t)(__ffsll(b) - 1);
         b &= b - 1;
         const BoxOrigin o = box_of(fd, t0 + k * w.stride, TY, TZ);
-        check_box<T, TY, TZ>(fd, conn, o, L);
+        check_box<T, TY, TZ>(fd, o, L);
         if (lead) done_v += box_vertices(fd, o, TY, TZ);
         __syncthreads();
       }
     }
   }
   if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
-}
-
-// Critical-point order: every consecutive pair, four per thread.
-constexpr int CP_BLOCK = 256;
-
-template <class T>
-__global__ void __launch_bounds__(CP_BLOCK) k_cpcmp(FieldDev fd) {
-  if (fd.st->done) return;
-  const uint32_t j = blockIdx.x * CP_BLOCK + threadIdx.x;
-  if (4u * j + 1 < (uint32_t)fd.K) cp_quad<T>(fd, j);
 }
 
 // ApplyBoundedEdits over the target marks.
@@ -136,7 +129,6 @@ __global__ void __launch_bounds__(64) k_state_reset(State *st, int64_t max_iters
   st->cert_bad = 0;
   st->nsaddle = 0;
   st->dense = 1;
-  st->prev_dense = 0;
   st->iterations = st->edit_ops = st->lossless_total = st->floor_total = st->edited_total = 0;
   st->residual = 0;
   st->max_iters = max_iters;
@@ -165,9 +157,11 @@ static int persistent_grid(const FieldDev &fd) {
   return fd.ntiles < g ? fd.ntiles : g;
 }
 
+// The check pass (with the critical-point order test of the reformulated
+// constraints), then, in original mode, the per-saddle event kernels.
 template <class T>
-static void launch_check_cpcmp(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,
-                               hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+static void launch_check_events(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,
+                                hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) (void)hipEventRecord(ev0, s);
 #define EXZ_BOX_CHECK(a, b)                                                                \
   if (fd.tile_y == a && fd.tile_z == b)                                                    \
@@ -175,11 +169,7 @@ static void launch_check_cpcmp(const FieldDev &fd, const uint32_t *conn, const u
   EXZ_BOX_SHAPES(EXZ_BOX_CHECK)
 #undef EXZ_BOX_CHECK
   if (ev1) (void)hipEventRecord(ev1, s);
-  if (fd.mode == 1)
-    (void)launch_original_events(fd, comp, s);
-  else if (fd.K > 1)
-    hipLaunchKernelGGL(k_cpcmp<T>, dim3((fd.K - 1 + 4 * CP_BLOCK - 1) / (4 * CP_BLOCK)),
-                       dim3(CP_BLOCK), 0, s, fd);
+  if (fd.mode == 1) (void)launch_original_events(fd, comp, s);
 }
 
 template <class T>
@@ -191,25 +181,9 @@ static void launch_apply(const FieldDev &fd, hipStream_t s) {
 template <class T>
 static void launch_phases(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,
                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  launch_check_cpcmp<T>(fd, conn, comp, s, ev0, ev1);
+  launch_check_events<T>(fd, conn, comp, s, ev0, ev1);
   launch_apply<T>(fd, s);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, fd);
-}
-
-hipError_t launch_cpcmp_only(const FieldDev &fd, hipStream_t s) {
-  if (fd.K > 1) {
-    const dim3 grid((fd.K - 1 + 4 * CP_BLOCK - 1) / (4 * CP_BLOCK));
-    if (fd.dtype == 0)
-      hipLaunchKernelGGL(k_cpcmp<float>, grid, dim3(CP_BLOCK), 0, s, fd);
-    else
-      hipLaunchKernelGGL(k_cpcmp<double>, grid, dim3(CP_BLOCK), 0, s, fd);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize(const FieldDev &fd, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, fd);
-  return hipGetLastError();
 }
 
 hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,
@@ -226,9 +200,9 @@ hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, const uint
 
 hipError_t launch_debug_check(const FieldDev &fd, const uint32_t *conn, hipStream_t s) {
   if (fd.dtype == 0)
-    launch_check_cpcmp<float>(fd, conn, nullptr, s, nullptr, nullptr);
+    launch_check_events<float>(fd, conn, nullptr, s, nullptr, nullptr);
   else
-    launch_check_cpcmp<double>(fd, conn, nullptr, s, nullptr, nullptr);
+    launch_check_events<double>(fd, conn, nullptr, s, nullptr, nullptr);
   return hipGetLastError();
 }
 

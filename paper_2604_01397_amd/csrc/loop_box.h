@@ -1,7 +1,7 @@
 // Device building blocks of one correction iteration on the 14-neighbour
 // Freudenthal mesh, shared by the single-field kernels (loop.hip) and the
-// batched ones (batch.hip): box staging, the per-vertex check, the
-// critical-point pair compare, the per-box apply and counter reduction.
+// batched ones (batch.hip): box staging, the per-vertex check (with the
+// critical-point order test), the apply and counter reduction.
 #pragma once
 
 #include "exz_internal.h"
@@ -101,10 +101,12 @@ __device__ __forceinline__ void stage_rows(const FieldDev &fd, const V *__restri
 
 // Requests of one vertex as a slot mask (bit SELF = the vertex itself).
 // P points at the LDS centre value of the vertex; pm / pp are the offsets
-// of the planes below / above relative to the centre plane.
+// of the planes below / above relative to the centre plane; dlt holds the
+// linear offset of every slot.
 template <class T>
 __device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint32_t *__restrict__ conn,
-                                                 const T *P, int pm, int pp, int x, int y, int z,
+                                                 const int32_t *dlt, const T *P, int pm, int pp,
+                                                 int x, int y, int z,
                                                  uint32_t i, uint32_t codeb, uint32_t lowf,
                                                  uint32_t &asc_v, uint32_t &desc_v, bool interior) {
   // Vertex indices of the neighbours, ascending: the slots with a negative
@@ -147,8 +149,8 @@ __device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint3
     lower |= (uint32_t)(q < 7 ? v[q] <= gi : v[q] < gi) << ORDER[q];
   }
   if (fd.mode == 1) {  // vertex indices are needed for path tracing only
-    asc_v = (uint32_t)((int)i + fd.dlt[asc]);
-    desc_v = (uint32_t)((int)i + fd.dlt[desc]);
+    asc_v = (uint32_t)((int)i + dlt[asc]);
+    desc_v = (uint32_t)((int)i + dlt[desc]);
   }
   const uint32_t code = codeb;
   const int asc_f = (int)(code & 15u), desc_f = (int)(code >> 4);
@@ -183,47 +185,73 @@ __device__ __forceinline__ uint32_t box_vertices(const FieldDev &fd, BoxOrigin o
 }
 
 // Adds the targets named by vertex i's request mask r (bit s: the neighbour
-// in slot s, bit SELF: i itself).
-__device__ __forceinline__ void post_targets(const FieldDev &fd, uint32_t i, uint32_t r) {
+// in slot s, at offset dlt[s]; bit SELF: i itself).
+__device__ __forceinline__ void post_targets(const FieldDev &fd, const int32_t *dlt, uint32_t i,
+                                             uint32_t r) {
   if ((r >> SELF) & 1u) mark_target(fd.tmark, i);
   r &= LOW_MASK;
   while (r) {
     const int s = __ffs(r) - 1;
     r &= r - 1;
-    mark_target(fd.tmark, (uint32_t)((int)i + fd.dlt[s]));
+    mark_target(fd.tmark, (uint32_t)((int)i + dlt[s]));
   }
 }
 
-// LDS of one check work-group: the staged box and the reference codes of
-// its own vertices (code byte | lower mask << 8).
+// LDS of one check work-group: the staged box, the reference codes of its
+// own vertices (code byte | lower mask << 8), the link connectivity bits and
+// the field's slot offsets.  With both tables in LDS the vertex loop issues
+// no global load (a per-lane index into the descriptor would be one), so no
+// wait in it waits for the successor gathers still in flight: a wait for a
+// vector memory load also waits for every older load and store.
+constexpr int CONN_WORDS = 512;  // one bit per 14-bit slot mask
 template <class T, int TY, int TZ>
 struct CheckLds {
   T S[Box<TY, TZ>::NE];
   uint32_t ref[TZ][64 * TY];
+  uint32_t conn[CONN_WORDS];
+  int32_t dlt[16];
 };
+
+// Copies the connectivity bits into LDS; the barrier of the first check_box
+// orders it before any use.
+template <class T, int TY, int TZ>
+__device__ __forceinline__ void load_conn(CheckLds<T, TY, TZ> &L, const uint32_t *__restrict__ conn) {
+  for (int k = threadIdx.y * 64 + threadIdx.x; k < CONN_WORDS; k += 64 * TY) L.conn[k] = conn[k];
+}
 
 // CheckConstraints on one box: stage g (and the box's reference codes), add
 // the targets every vertex names to the target set (and, in original mode,
-// write g's descent / ascent pointers).  The caller synchronises the block
-// after it.
+// write g's descent / ascent pointers).  With the reformulated event
+// constraints (Sec. 4.3) every critical point of f is also compared with the
+// next critical point in f's order: when g inverts the pair, the lower one
+// (this vertex) goes down.  The successor's value is gathered from g while
+// the box is checked.  The caller synchronises the block after it.
 template <class T, int TY, int TZ>
-__device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__restrict__ conn,
-                                          BoxOrigin o, CheckLds<T, TY, TZ> &L) {
+__device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, CheckLds<T, TY, TZ> &L) {
   using B = Box<TY, TZ>;
   const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx;
   const int x = o.x0 + lx, y = o.y0 + ly;
   const bool col = x < fd.nx && y < fd.ny;
   const uint32_t plane = (uint32_t)fd.nx * (uint32_t)fd.ny;
   const uint32_t i0 = (uint32_t)x + (uint32_t)fd.nx * ((uint32_t)y + (uint32_t)fd.ny * (uint32_t)o.z0);
-  uint32_t refs[TZ];
+  const bool pairs = fd.mode != 1;  // reformulated event constraints
+  uint32_t refs[TZ], sc[TZ];
 #pragma unroll
   for (int k = 0; k < TZ; ++k) {  // issued with the staging loads, unconditionally
     const bool in = col && o.z0 + k < fd.nz;
     const uint32_t idx = in ? i0 + k * plane : 0u;
     const uint32_t cb = glob(fd.code)[idx], lb = glob(fd.low)[idx];
     refs[k] = cb | (lb << 8);
+    sc[k] = pairs && in ? glob(fd.succ)[idx] : NONE;
+  }
+  if (tid == 0) {  // constant indices: scalar loads, ordered by the barrier below
+#pragma unroll
+    for (int q = 0; q < 16; ++q) L.dlt[q] = fd.dlt[q];
   }
   stage_rows<TY, TZ>(fd, (const T *)fd.g, L.S, o);
+  T gs[TZ];  // successor values, in flight during the check
+#pragma unroll
+  for (int k = 0; k < TZ; ++k) gs[k] = sc[k] != NONE ? glob((const T *)fd.g)[sc[k]] : T(0);
 #pragma unroll
   for (int k = 0; k < TZ; ++k) L.ref[k][tid] = refs[k];
   const bool interior = o.x0 >= 1 && o.x0 + 64 <= fd.nx - 1 && o.y0 >= 1 &&
@@ -237,43 +265,26 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, const uint32_t *__
       const T *c = L.S + (k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1;
       const uint32_t rf = L.ref[k][tid];
       uint32_t av = 0, dv = 0;
-      const uint32_t r = check_vertex<T>(fd, conn, c, -B::PLANE, B::PLANE, x, y, z, i, rf & 255u,
-                                         rf >> 8, av, dv, interior);
-      if (r) post_targets(fd, i, r);
+      const uint32_t r = check_vertex<T>(fd, L.conn, L.dlt, c, -B::PLANE, B::PLANE, x, y, z, i,
+                                         rf & 255u, rf >> 8, av, dv, interior);
+      if (r) post_targets(fd, L.dlt, i, r);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
         glob(fd.lab)[i] = dv;
         glob(fd.lab)[fd.n + i] = (uint32_t)fd.n + av;
       }
     }
   }
-}
-
-// Reformulated event constraints: consecutive critical points in f's order
-// must keep their order in g; an inverted pair decreases the lower one.
-// Values are finite, so b > a settles most pairs without the vertex indices.
-__device__ __forceinline__ void mark_box_range(const FieldDev &fd, uint32_t x0, uint32_t x1,
-                                               uint32_t y, uint32_t z);
-
-template <class T>
-__device__ __forceinline__ void cp_pair_vals(const FieldDev &fd, uint32_t r, T a, T b) {
-  if (b > a) return;
-  const uint32_t ia = glob(fd.cp_idx)[r], ib = glob(fd.cp_idx)[r + 1];
-  if (!sos_lt(b, ib, a, ia)) return;
-  mark_target(fd.tmark, ia);
-  if (fd.fused && fd.frontier) {  // the boxes whose check reads the target
-    const uint32_t x = ia % (uint32_t)fd.nx, q = ia / (uint32_t)fd.nx;
-    mark_box_range(fd, x, x, q % (uint32_t)fd.ny, q / (uint32_t)fd.ny);
+#pragma unroll
+  for (int k = 0; k < TZ; ++k) {
+    if (sc[k] == NONE) continue;
+    const uint32_t i = i0 + k * plane;
+    const T a = L.S[(k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1];
+    // values are finite, so b > a settles most pairs without the indices
+    if (!(gs[k] > a) && sos_lt(gs[k], sc[k], a, i)) mark_target(fd.tmark, i);
   }
 }
 
-template <class T>
-__device__ __forceinline__ void cp_pair(const FieldDev &fd, uint32_t r) {
-  const T *V = (const T *)fd.cp_val;
-  cp_pair_vals<T>(fd, r, glob(V)[r], glob(V)[r + 1]);
-}
-
-// Pairs 4j .. 4j+3 (those with a successor): five values, read as one
-// aligned block of four plus the next one.
+// Four values from an aligned block (vector loads and stores).
 template <class T> struct Vec4;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -283,6 +294,11 @@ template <> struct Vec4<float> {
     const f32x4 v = *glob(reinterpret_cast<const f32x4 *>(p));
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   }
+  static __device__ __forceinline__ void store(float *p, const float *o) {
+    f32x4 v;
+    v.x = o[0]; v.y = o[1]; v.z = o[2]; v.w = o[3];
+    *glob(reinterpret_cast<f32x4 *>(p)) = v;
+  }
 };
 template <> struct Vec4<double> {
   static __device__ __forceinline__ void load(const double *p, double *o) {
@@ -290,22 +306,13 @@ template <> struct Vec4<double> {
     const f64x2 b = glob(reinterpret_cast<const f64x2 *>(p))[1];
     o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
   }
-};
-
-template <class T>
-__device__ __forceinline__ void cp_quad(const FieldDev &fd, uint32_t j) {
-  const T *V = (const T *)fd.cp_val;
-  const uint32_t K = (uint32_t)fd.K, r0 = 4u * j;
-  T v[5];
-  if (r0 + 4 < K) {
-    Vec4<T>::load(V + r0, v);
-    v[4] = glob(V)[r0 + 4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) cp_pair_vals<T>(fd, r0 + k, v[k], v[k + 1]);
-  } else {
-    for (uint32_t r = r0; r + 1 < K; ++r) cp_pair<T>(fd, r);
+  static __device__ __forceinline__ void store(double *p, const double *o) {
+    f64x2 a, b;
+    a.x = o[0]; a.y = o[1]; b.x = o[2]; b.y = o[3];
+    glob(reinterpret_cast<f64x2 *>(p))[0] = a;
+    glob(reinterpret_cast<f64x2 *>(p))[1] = b;
   }
-}
+};
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
@@ -348,64 +355,97 @@ __device__ __forceinline__ uint32_t quad_marks(const FieldDev &fd, uint32_t q) {
   return *glob(reinterpret_cast<const uint32_t *>(fd.tmark + 4u * q));
 }
 
-// ApplyBoundedEdits on the vertices v .. v+3 whose mark bytes in m are set
-// (m != 0); clears the marks and adds this thread's counts to ec.  The
-// loads of all four go out together (unmarked ones read vertex v, which is
-// valid).  Returns the vertices whose value or count moved, as bits 0..3.
+// Inputs of one quad v .. v+3 of apply: value, f, edit count and (frontier
+// passes) the box of the previous critical point of each vertex.
 template <class T>
-__device__ __forceinline__ uint32_t apply_quad(const FieldDev &fd, uint32_t v, uint32_t m,
-                                               EditCount &ec) {
-  T *G = (T *)fd.g;
+struct QuadIn {
+  T g[4], f[4];
+  uint32_t c[4], pb[4];
+};
+
+// Loads the inputs of the quad at v whose mark bytes are m (m != 0): vector
+// loads when the whole quad is in the field and aligned, else one load per
+// vertex (unmarked ones read vertex v, which is valid).
+template <class T>
+__device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32_t m, QuadIn<T> &d) {
+  const T *G = (const T *)fd.g;
   const T *F = (const T *)fd.f;
-  const T xiT = (T)fd.xiT, delta = (T)fd.delta;
-  T g0[4], fv[4];
-  uint32_t c0[4], rk[4];
-  if (fd.vec && v + 3 < (uint32_t)fd.n) {  // whole quad: vector loads
-    Vec4<T>::load(G + v, g0);
-    Vec4<T>::load(F + v, fv);
+  if (fd.vec && v + 3 < (uint32_t)fd.n) {
+    Vec4<T>::load(G + v, d.g);
+    Vec4<T>::load(F + v, d.f);
     const uint32_t c4 = *glob(reinterpret_cast<const uint32_t *>(fd.cnt + v));
-    const u32x4 r4 = *glob(reinterpret_cast<const u32x4 *>(fd.rank_of + v));
 #pragma unroll
-    for (int c = 0; c < 4; ++c) c0[c] = (c4 >> (8 * c)) & 255u;
-    rk[0] = r4.x;
-    rk[1] = r4.y;
-    rk[2] = r4.z;
-    rk[3] = r4.w;
+    for (int c = 0; c < 4; ++c) d.c[c] = (c4 >> (8 * c)) & 255u;
+    if (fd.frontier) {
+      const u32x4 p4 = *glob(reinterpret_cast<const u32x4 *>(fd.pred_box + v));
+      d.pb[0] = p4.x;
+      d.pb[1] = p4.y;
+      d.pb[2] = p4.z;
+      d.pb[3] = p4.w;
+    }
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const uint32_t t = ((m >> (8 * c)) & 255u) ? v + c : v;
-      g0[c] = glob(G)[t];
-      fv[c] = glob(F)[t];
-      c0[c] = glob(fd.cnt)[t];
-      rk[c] = glob(fd.rank_of)[t];
+      d.g[c] = glob(G)[t];
+      d.f[c] = glob(F)[t];
+      d.c[c] = glob(fd.cnt)[t];
+      if (fd.frontier) d.pb[c] = glob(fd.pred_box)[t];
     }
   }
+}
+
+// ApplyBoundedEdits on the vertices v .. v+3 whose mark bytes in m are set,
+// from the inputs d; clears the marks and adds this thread's counts to ec.
+// A whole aligned quad is written back with one vector store of its values
+// and one 32-bit store of its counts (unmarked vertices keep theirs).
+// Returns the vertices whose value or count moved, as bits 0..3.
+template <class T>
+__device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, uint32_t m,
+                                              const QuadIn<T> &d, EditCount &ec) {
+  T *G = (T *)fd.g;
+  const T xiT = (T)fd.xiT, delta = (T)fd.delta;
   *glob(reinterpret_cast<uint32_t *>(fd.tmark + v)) = 0;
-  uint32_t moved = 0;
+  uint32_t moved = 0, cw = 0;
+  T gn[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
+    gn[c] = d.g[c];
+    cw |= d.c[c] << (8 * c);
     if (!((m >> (8 * c)) & 255u)) continue;
-    const uint32_t t = v + c;
     ++ec.v[0];
-    const T L = lower_bound(fv[c], xiT);
-    if (g0[c] == L) continue;  // at the floor: blocked
-    const uint32_t cn = c0[c] + 1;
-    glob(fd.cnt)[t] = (uint8_t)cn;
+    const T L = lower_bound(d.f[c], xiT);
+    if (d.g[c] == L) continue;  // at the floor: blocked
+    const uint32_t cn = d.c[c] + 1;
+    cw = (cw & ~(255u << (8 * c))) | ((cn & 255u) << (8 * c));
     T nv;
     if (cn > (uint32_t)fd.N) {
       nv = L;  // (N+1)-th edit: store the lower bound itself
       ++ec.v[2];
     } else {
-      const T cand = g0[c] - delta;
+      const T cand = d.g[c] - delta;
       nv = cand < L ? L : cand;
     }
-    glob(G)[t] = nv;
-    if (rk[c] != 0xFFFFFFFFu) glob((T *)fd.cp_val)[rk[c]] = nv;
+    gn[c] = nv;
+    // the previous critical point in f's order compares itself with t
+    if (fd.frontier && d.pb[c] != NONE) glob(fd.bdirty)[d.pb[c]] = 1;
     moved |= 1u << c;
     ++ec.v[1];
     ec.v[3] += nv == L;
     ec.v[4] += cn == 1;
+  }
+  if (moved) {
+    if (fd.vec && v + 3 < (uint32_t)fd.n) {
+      Vec4<T>::store(G + v, gn);
+      *glob(reinterpret_cast<uint32_t *>(fd.cnt + v)) = cw;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (!((moved >> c) & 1u)) continue;
+        glob(G)[v + c] = gn[c];
+        glob(fd.cnt)[v + c] = (uint8_t)(cw >> (8 * c));
+      }
+    }
   }
   return moved;
 }
@@ -434,18 +474,29 @@ __device__ __forceinline__ void mark_moved_boxes(const FieldDev &fd, uint32_t v,
   }
 }
 
-// ApplyBoundedEdits over quads q = q0, q0 + stride, ... (< nq): the marks of
-// the next quad are fetched before the current one is edited.
+// ApplyBoundedEdits over quads q = q0, q0 + stride, ... (< nq), two at a
+// time: the inputs of both go out before either is edited, and the marks of
+// the next two are fetched before the current ones are edited.
 template <class T>
 __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uint32_t stride,
                                             uint32_t nq, EditCount &ec) {
-  uint32_t m = q0 < nq ? quad_marks(fd, q0) : 0u;
-  for (uint32_t q = q0; q < nq; q += stride) {
-    const uint32_t qn = q + stride;
-    const uint32_t mn = qn < nq ? quad_marks(fd, qn) : 0u;
-    const uint32_t moved = m ? apply_quad<T>(fd, 4u * q, m, ec) : 0u;
-    if (fd.frontier) mark_moved_boxes(fd, 4u * q, moved);
-    m = mn;
+  uint32_t ma = q0 < nq ? quad_marks(fd, q0) : 0u;
+  uint32_t mb = q0 + stride < nq ? quad_marks(fd, q0 + stride) : 0u;
+  for (uint32_t q = q0; q < nq; q += 2 * stride) {
+    const uint32_t qb = q + stride, qa2 = q + 2 * stride, qb2 = q + 3 * stride;
+    const uint32_t ma2 = qa2 < nq ? quad_marks(fd, qa2) : 0u;
+    const uint32_t mb2 = qb2 < nq ? quad_marks(fd, qb2) : 0u;
+    QuadIn<T> a, b;
+    if (ma) load_quad<T>(fd, 4u * q, ma, a);
+    if (mb) load_quad<T>(fd, 4u * qb, mb, b);
+    const uint32_t mva = ma ? edit_quad<T>(fd, 4u * q, ma, a, ec) : 0u;
+    const uint32_t mvb = mb ? edit_quad<T>(fd, 4u * qb, mb, b, ec) : 0u;
+    if (fd.frontier) {
+      mark_moved_boxes(fd, 4u * q, mva);
+      mark_moved_boxes(fd, 4u * qb, mvb);
+    }
+    ma = ma2;
+    mb = mb2;
   }
 }
 
@@ -472,8 +523,7 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
   State *st = fd.st;
   if (st->done) return;
   const int lane = threadIdx.x;
-  const int64_t pass = st->passes;  // passes before this one
-  if (lane == 0) st->passes = pass + 1;
+  if (lane == 0) st->passes += 1;
   uint32_t v[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -482,20 +532,12 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
   }
   if (lane != 0) return;
   const uint32_t nt = v[0], ch = v[1];
-  if (fd.fused && pass == 0) {  // a fused first pass only checks: nothing applied yet
-    st->prev_dense = st->dense;
-    st->dense = 0;
-    return;
-  }
   if (fd.trace && st->iterations < fd.trace_cap) {
     fd.trace[2 * st->iterations] = nt;
     fd.trace[2 * st->iterations + 1] = ch;
   }
   // Were the targets just applied named by a check that covered every box?
-  // (A fused pass applies the targets of the previous pass's check.)
-  const bool complete = fd.fused ? st->prev_dense != 0 : st->dense != 0;
-  if (fd.fused) st->prev_dense = st->dense;
-  if (ch == 0 && fd.frontier && !complete) {
+  if (ch == 0 && fd.frontier && !st->dense) {
     // A frontier pass skips boxes whose requests were all blocked, so it
     // cannot tell a fixpoint from convergence (or count the residual): dense
     // passes over the unchanged field settle it.

@@ -22,8 +22,6 @@
 
 namespace exz {
 
-constexpr uint32_t NONE = 0xFFFFFFFFu;
-
 // --- saddle order: ranks (in the CP order) of the saddles of f -------------
 
 __global__ void k_saddle_flags(FieldDev fd, uint32_t *flags) {
@@ -142,13 +140,12 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   if (k >= ns) return;
   const T *G = (const T *)fd.g;
   const T *F = (const T *)fd.f;
-  const T *V = (const T *)fd.cp_val;
   const uint32_t rk = fd.sad_rank[k];
   const uint32_t s = fd.cp_idx[rk];
   // C2: saddle order
   if (k + 1 < ns) {
-    const uint32_t rn = fd.sad_rank[k + 1];
-    if (sos_lt(V[rn], fd.cp_idx[rn], V[rk], s)) mark_target(fd.tmark, s);
+    const uint32_t sn = fd.cp_idx[fd.sad_rank[k + 1]];
+    if (sos_lt(G[sn], sn, G[s], s)) mark_target(fd.tmark, s);
   }
   // C3: selected extrema along the integral paths of g
   const uint32_t mf = fd.sel_f[2 * k], Mf = fd.sel_f[2 * k + 1];

@@ -122,7 +122,8 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd, const uint8_
     }
     fd.code[i] = (uint8_t)(asc | (desc << 4));
     fd.low[i] = (uint16_t)low;
-    fd.rank_of[i] = 0xFFFFFFFFu;
+    fd.succ[i] = NONE;
+    fd.pred_box[i] = NONE;
     if (fd.g != fd.g_hat) ((T *)fd.g)[i] = gi;
     if (!fd.resume) fd.cnt[i] = 0;
   }
@@ -282,27 +283,31 @@ hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *, void *keys, hi
   return hipGetLastError();
 }
 
+// Check box (of the field's box shape) that holds vertex v.
+__device__ __forceinline__ uint32_t box_index(const FieldDev &fd, uint32_t v) {
+  const uint32_t x = v % (uint32_t)fd.nx, q = v / (uint32_t)fd.nx;
+  const uint32_t y = q % (uint32_t)fd.ny, z = q / (uint32_t)fd.ny;
+  return (x >> 6) + (uint32_t)fd.tiles_x * ((y >> fd.ty_shift) + (uint32_t)fd.tiles_y * (z >> fd.tz_shift));
+}
+
 // After the stable sort of the keys (payload = vertex-order index): the
-// rank -> vertex map, the vertex order -> rank map and the current values.
-template <class T>
+// rank -> vertex map, each critical point's successor in f's order and the
+// box of its predecessor.
 __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint32_t *sorted_vo) {
   const uint32_t r = blockIdx.x * SETUP_BLOCK + threadIdx.x;
-  if (r >= (uint32_t)fd.K) return;
-  const uint32_t vo = sorted_vo[r];
-  const uint32_t v = fd.cp_vtx[vo];
+  const uint32_t K = (uint32_t)fd.K;
+  if (r >= K) return;
+  const uint32_t v = fd.cp_vtx[sorted_vo[r]];
   fd.cp_idx[r] = v;
-  fd.rank_of[v] = r;
-  ((T *)fd.cp_val)[r] = ((const T *)fd.g)[v];
+  fd.succ[v] = r + 1 < K ? fd.cp_vtx[sorted_vo[r + 1]] : NONE;
+  fd.pred_box[v] = r > 0 ? box_index(fd, fd.cp_vtx[sorted_vo[r - 1]]) : NONE;
 }
 
 hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, const uint8_t *,
                           hipStream_t s) {
   if (fd.K == 0) return hipSuccess;
   const int grid = (fd.K + SETUP_BLOCK - 1) / SETUP_BLOCK;
-  if (fd.dtype == 0)
-    hipLaunchKernelGGL(k_cp_init<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
-  else
-    hipLaunchKernelGGL(k_cp_init<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
+  hipLaunchKernelGGL(k_cp_init, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
   return hipGetLastError();
 }
 

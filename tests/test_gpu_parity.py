@@ -302,9 +302,8 @@ def test_frontier_matches_dense_and_oracle(name, make):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c = make()
-    # dense: separate check and apply launches on every box; front: the
-    # defaults (fused passes, frontier)
-    dense = exactz.Context(0, profile=1, frontier=0, fused=0)
+    # dense: every pass checks every box; front: the default frontier passes
+    dense = exactz.Context(0, profile=1, frontier=0)
     front = exactz.Context(0, profile=1, frontier=1)
     try:
         f, g = _dev(c.f), _dev(c.g_hat)
@@ -398,12 +397,13 @@ def test_unaligned_buffers_match(ctx):
 
 
 # ----------------------------------------------------------------------------
-# fused passes (apply of the previous pass's targets + check in one sweep)
-# against separate check and apply launches
+# frontier passes (boxes flagged by the last apply, including the box of the
+# previous critical point of every moved vertex) against dense passes, for
+# every box shape and for runs cut short by the iteration cap
 
 
 @pytest.mark.parametrize("tile", [0, 202, 404, 408, 804, 1602, 101, 401])
-def test_fused_matches_separate(ctx, tile):
+def test_frontier_matches_dense_per_box(ctx, tile):
     cases = [synth.case_grf3d((29, 35, 70), seed=61, rel=1e-3),
              synth.case_grf3d(40, seed=62, rel=1e-4, quantizer="lorenzo"),
              synth.case_gauss2d(140, seed=63, rel=1e-3, dtype=np.float64)]
@@ -412,9 +412,9 @@ def test_fused_matches_separate(ctx, tile):
         for c in cases:
             f, g = _dev(c.f), _dev(c.g_hat)
             print("case:", c.name, "tile", tile, flush=True)
-            ctx.set_option("fused", 0)
+            ctx.set_option("frontier", 0)
             ref, cref, rref = ctx.correct(f, g, c.xi)
-            ctx.set_option("fused", 1)
+            ctx.set_option("frontier", 1)
             out, cout, r = ctx.correct(f, g, c.xi)
             torch.cuda.synchronize()
             assert torch.equal(out, ref) and torch.equal(cout, cref), c.name
@@ -423,12 +423,12 @@ def test_fused_matches_separate(ctx, tile):
                 assert r[k] == rref[k], (c.name, k, r[k], rref[k])
             for mi in (1, 2, 5):
                 o1, c1, r1 = ctx.correct(f, g, c.xi, max_iters=mi)
-                ctx.set_option("fused", 0)
+                ctx.set_option("frontier", 0)
                 o0, c0, r0 = ctx.correct(f, g, c.xi, max_iters=mi)
-                ctx.set_option("fused", 1)
+                ctx.set_option("frontier", 1)
                 torch.cuda.synchronize()
                 assert torch.equal(o1, o0) and torch.equal(c1, c0), (c.name, mi)
                 assert (r1["status"], r1["iterations"]) == (r0["status"], r0["iterations"])
     finally:
         ctx.set_option("tile", 0)
-        ctx.set_option("fused", 1)
+        ctx.set_option("frontier", 1)
