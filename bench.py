@@ -9,10 +9,12 @@ critical points, loop to the fixpoint) from g_hat into a separate output,
 with f and g_hat already resident in HBM.
 
 Prints one JSON line.  ``roofline`` is for the dominant kernel (the check
-pass): algorithmic bytes ((b + 1) bytes per vertex checked: the field value
-and the reference code byte; a frontier pass checks only the boxes the last
-apply touched) over the check launches' device time, measured with HIP
-events on the library's stream during the timed steps.
+pass): algorithmic bytes over the check launches' device time, measured with
+HIP events on the library's stream during the timed steps.  Per vertex
+checked the method reads its value (b bytes) and f's reference (3 bytes:
+steepest-pair code and lower-link mask); per critical point also the index
+(4 bytes) and value (b bytes) of its successor in f's order.  A frontier
+pass checks only the boxes the last apply touched.
 ``cpu_baseline`` is the CPU oracle, single thread, on a bounded sample of
 the same input (a 128^3 sub-block of the field, corrected to convergence).
 """
@@ -250,8 +252,10 @@ def main():
     b = case.f.itemsize
     value = n * b / (ms * 1e-3) / 1e9
     avg_check_ms = check_ms / max(check_n, 1)
-    algo_bytes = (b + 1) * check_v / max(check_n, 1)  # per launch, on average
-    achieved = (b + 1) * check_v / (check_ms * 1e-3) / 1e9
+    # bytes per vertex checked; critical points at their share of the field
+    per_vertex = (b + 3) + (4 + b) * res["num_critical"] / n
+    algo_bytes = per_vertex * check_v / max(check_n, 1)  # per launch, on average
+    achieved = per_vertex * check_v / (check_ms * 1e-3) / 1e9
     line = {
         "metric": "GB/s of field corrected on 1 MI355X (plain vs batched); p50/p99 job latency",
         "value": round(value, 3),
@@ -274,6 +278,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.edge), "avg_launch_ms": round(avg_check_ms, 5),
                      "launches": check_n, "bytes_per_launch": round(algo_bytes),
+                     "bytes_per_vertex": round(per_vertex, 3),
                      "vertices_checked_per_step": check_v // args.steps},
     }
     ctx.close()

@@ -202,7 +202,7 @@ void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]) {
   off[1] = L.add(4 * (size_t)Kc);  // cp_vtx
   off[2] = 0;
   off[3] = L.add(4 * (size_t)Kc);  // cp_idx
-  off[4] = 0;
+  off[4] = L.add(b * Kc);          // cpv
   off[5] = L.add(kb * Kc);         // keys
   off[6] = L.add(kb * Kc);         // keys tmp
   off[7] = L.add(4 * (size_t)Kc);  // vals
@@ -258,6 +258,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   char *bb = (char *)B.take(LB.total);
   fd.cp_vtx = (uint32_t *)(bb + ob[1]);
   fd.cp_idx = (uint32_t *)(bb + ob[3]);
+  fd.cpv = bb + ob[4];
   void *keys = bb + ob[5];
   void *keys_tmp = bb + ob[6];
   uint32_t *vals = (uint32_t *)(bb + ob[7]);

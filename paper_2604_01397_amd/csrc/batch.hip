@@ -515,6 +515,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       char *b = Bm + baseB[k];
       fd.cp_vtx = (uint32_t *)(b + ob[k][1]);
       fd.cp_idx = (uint32_t *)(b + ob[k][3]);
+      fd.cpv = b + ob[k][4];
       const uint32_t K = (uint32_t)fd.K;
       if (K > 0) {
         const size_t hw = radix_hist_words(K);

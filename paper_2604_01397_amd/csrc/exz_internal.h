@@ -28,6 +28,8 @@ constexpr int DZS[NSLOT] = {0, 0, 0, 0, 0, 0, +1, -1, +1, -1, +1, -1, +1, -1};
 constexpr uint32_t LOW_SADDLE = 1u << 15;
 constexpr uint32_t LOW_MASK = 0x3FFFu;
 constexpr uint32_t NONE = 0xFFFFFFFFu;  // no vertex / no box
+constexpr uint32_t SUCC_SLOT = 0x7FFFFFFFu;
+constexpr uint32_t SUCC_BELOW = 0x80000000u;
 
 enum Done : int32_t { RUNNING = 0, CONVERGED = 1, STUCK = 2, MAXITERS = 3 };
 constexpr int MAX_JUMP_ROUNDS = 34;  // pointer jumping over < 2^32 labels
@@ -89,8 +91,11 @@ struct FieldDev {
   unsigned long long *cpbits;
   uint32_t *cpoff;      // nchunk + 1 exclusive prefix counts
   uint32_t *cp_vtx;     // K, vertex order -> vertex
-  uint32_t *succ;       // n: the next critical point of f in f's order, NONE otherwise
+  uint32_t *succ;       // n: SUCC_SLOT bits: vertex-order slot of the next critical point
+                        // of f in f's order, SUCC_BELOW: its index is below this one's;
+                        // NONE for the last critical point and for other vertices
   uint32_t *pred_box;   // n: box holding the previous critical point of f, NONE otherwise
+  void *cpv;            // K: current value of every critical point of f, in vertex order
   uint32_t *cp_idx;     // K, rank -> vertex
   uint32_t *sad_rank;   // saddle order -> rank in the CP order (K capacity)
   uint32_t *sel_f;      // 2 per saddle: selections in f (join, split) or ~0

@@ -249,9 +249,12 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, Check
     for (int q = 0; q < 16; ++q) L.dlt[q] = fd.dlt[q];
   }
   stage_rows<TY, TZ>(fd, (const T *)fd.g, L.S, o);
-  T gs[TZ];  // successor values, in flight during the check
+  // successor values, in flight during the check, from the compact array of
+  // critical-point values (small enough to stay in the memory-side cache)
+  T gs[TZ];
 #pragma unroll
-  for (int k = 0; k < TZ; ++k) gs[k] = sc[k] != NONE ? glob((const T *)fd.g)[sc[k]] : T(0);
+  for (int k = 0; k < TZ; ++k)
+    gs[k] = sc[k] != NONE ? glob((const T *)fd.cpv)[sc[k] & SUCC_SLOT] : T(0);
 #pragma unroll
   for (int k = 0; k < TZ; ++k) L.ref[k][tid] = refs[k];
   const bool interior = o.x0 >= 1 && o.x0 + 64 <= fd.nx - 1 && o.y0 >= 1 &&
@@ -277,10 +280,10 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, Check
 #pragma unroll
   for (int k = 0; k < TZ; ++k) {
     if (sc[k] == NONE) continue;
-    const uint32_t i = i0 + k * plane;
     const T a = L.S[(k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1];
-    // values are finite, so b > a settles most pairs without the indices
-    if (!(gs[k] > a) && sos_lt(gs[k], sc[k], a, i)) mark_target(fd.tmark, i);
+    // the successor is below in the simulated order: a lower value, or an
+    // equal one at a lower vertex index
+    if (gs[k] < a || (gs[k] == a && (sc[k] & SUCC_BELOW))) mark_target(fd.tmark, i0 + k * plane);
   }
 }
 
@@ -356,11 +359,14 @@ __device__ __forceinline__ uint32_t quad_marks(const FieldDev &fd, uint32_t q) {
 }
 
 // Inputs of one quad v .. v+3 of apply: value, f, edit count and (frontier
-// passes) the box of the previous critical point of each vertex.
+// passes) the box of the previous critical point of each vertex; with the
+// reformulated constraints also which of them are critical points of f
+// (bits 0..3) and the vertex-order slot of the first of those.
 template <class T>
 struct QuadIn {
   T g[4], f[4];
   uint32_t c[4], pb[4];
+  uint32_t cpm, vo0;
 };
 
 // Loads the inputs of the quad at v whose mark bytes are m (m != 0): vector
@@ -392,6 +398,12 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32
       d.c[c] = glob(fd.cnt)[t];
       if (fd.frontier) d.pb[c] = glob(fd.pred_box)[t];
     }
+  }
+  if (fd.mode != 1) {  // a quad lies in one 64-vertex chunk of the bitmask
+    const uint32_t ch = v >> 6, sh = v & 63u;
+    const unsigned long long bits = glob(fd.cpbits)[ch];
+    d.cpm = (uint32_t)(bits >> sh) & 15u;
+    d.vo0 = glob(fd.cpoff)[ch] + (uint32_t)__popcll(bits & ((1ull << sh) - 1ull));
   }
 }
 
@@ -427,6 +439,9 @@ __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, ui
       nv = cand < L ? L : cand;
     }
     gn[c] = nv;
+    // the compact copy of critical-point values that the order test reads
+    if (fd.mode != 1 && ((d.cpm >> c) & 1u))
+      glob((T *)fd.cpv)[d.vo0 + (uint32_t)__popc(d.cpm & ((1u << c) - 1u))] = nv;
     // the previous critical point in f's order compares itself with t
     if (fd.frontier && d.pb[c] != NONE) glob(fd.bdirty)[d.pb[c]] = 1;
     moved |= 1u << c;
@@ -474,29 +489,25 @@ __device__ __forceinline__ void mark_moved_boxes(const FieldDev &fd, uint32_t v,
   }
 }
 
-// ApplyBoundedEdits over quads q = q0, q0 + stride, ... (< nq), two at a
-// time: the inputs of both go out before either is edited, and the marks of
-// the next two are fetched before the current ones are edited.
+// ApplyBoundedEdits over quads q = q0, q0 + stride, ... (< nq): the marks
+// of the next quad are fetched before the current one is edited.  One quad
+// per thread at a time keeps the register count, and so the number of waves
+// in flight, high.
 template <class T>
 __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uint32_t stride,
                                             uint32_t nq, EditCount &ec) {
-  uint32_t ma = q0 < nq ? quad_marks(fd, q0) : 0u;
-  uint32_t mb = q0 + stride < nq ? quad_marks(fd, q0 + stride) : 0u;
-  for (uint32_t q = q0; q < nq; q += 2 * stride) {
-    const uint32_t qb = q + stride, qa2 = q + 2 * stride, qb2 = q + 3 * stride;
-    const uint32_t ma2 = qa2 < nq ? quad_marks(fd, qa2) : 0u;
-    const uint32_t mb2 = qb2 < nq ? quad_marks(fd, qb2) : 0u;
-    QuadIn<T> a, b;
-    if (ma) load_quad<T>(fd, 4u * q, ma, a);
-    if (mb) load_quad<T>(fd, 4u * qb, mb, b);
-    const uint32_t mva = ma ? edit_quad<T>(fd, 4u * q, ma, a, ec) : 0u;
-    const uint32_t mvb = mb ? edit_quad<T>(fd, 4u * qb, mb, b, ec) : 0u;
-    if (fd.frontier) {
-      mark_moved_boxes(fd, 4u * q, mva);
-      mark_moved_boxes(fd, 4u * qb, mvb);
+  uint32_t m = q0 < nq ? quad_marks(fd, q0) : 0u;
+  for (uint32_t q = q0; q < nq; q += stride) {
+    const uint32_t qn = q + stride;
+    const uint32_t mn = qn < nq ? quad_marks(fd, qn) : 0u;
+    uint32_t moved = 0;
+    if (m) {
+      QuadIn<T> d;
+      load_quad<T>(fd, 4u * q, m, d);
+      moved = edit_quad<T>(fd, 4u * q, m, d, ec);
     }
-    ma = ma2;
-    mb = mb2;
+    if (fd.frontier) mark_moved_boxes(fd, 4u * q, moved);
+    m = mn;
   }
 }
 

@@ -270,6 +270,7 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_compact(FieldDev fd, void *k
   const T *F = (const T *)fd.f;
   const uint32_t vo = cp_order(fd.cpbits, fd.cpoff, i);
   fd.cp_vtx[vo] = i;
+  ((T *)fd.cpv)[vo] = ((const T *)fd.g)[i];
   using K = decltype(sort_key(T(0)));
   ((K *)keys_)[vo] = sort_key(F[i]);
 }
@@ -290,16 +291,23 @@ __device__ __forceinline__ uint32_t box_index(const FieldDev &fd, uint32_t v) {
   return (x >> 6) + (uint32_t)fd.tiles_x * ((y >> fd.ty_shift) + (uint32_t)fd.tiles_y * (z >> fd.tz_shift));
 }
 
-// After the stable sort of the keys (payload = vertex-order index): the
-// rank -> vertex map, each critical point's successor in f's order and the
-// box of its predecessor.
+// After the stable sort of the keys (payload = vertex-order slot): the
+// rank -> vertex map, each critical point's successor in f's order (its
+// slot, and whether its vertex index is the lower one: slots follow vertex
+// order) and the box of its predecessor.
 __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint32_t *sorted_vo) {
   const uint32_t r = blockIdx.x * SETUP_BLOCK + threadIdx.x;
   const uint32_t K = (uint32_t)fd.K;
   if (r >= K) return;
-  const uint32_t v = fd.cp_vtx[sorted_vo[r]];
+  const uint32_t vo = sorted_vo[r];
+  const uint32_t v = fd.cp_vtx[vo];
   fd.cp_idx[r] = v;
-  fd.succ[v] = r + 1 < K ? fd.cp_vtx[sorted_vo[r + 1]] : NONE;
+  if (r + 1 < K) {
+    const uint32_t so = sorted_vo[r + 1];
+    fd.succ[v] = so | (so < vo ? SUCC_BELOW : 0u);
+  } else {
+    fd.succ[v] = NONE;
+  }
   fd.pred_box[v] = r > 0 ? box_index(fd, fd.cp_vtx[sorted_vo[r - 1]]) : NONE;
 }
 

@@ -7,8 +7,8 @@
 // against (Sec. 4.3).
 //
 // One pass = per-block digit histograms (digit-major), an exclusive scan of
-// the histograms, and a stable scatter in which each wave ranks equal digits
-// with eight ballots.
+// the histograms, and a stable scatter that orders each tile by digit in LDS
+// before writing it out in coalesced runs.
 #include "exz_internal.h"
 
 namespace exz {
@@ -33,18 +33,46 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const K *keys, uint32_t co
   hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile of RS_TILE elements.  The tile is first
+// ordered by digit in LDS (stable: each wave ranks equal digits of its 64
+// elements with eight ballots, waves and rounds follow element order), then
+// written out run by run: consecutive threads write consecutive positions of
+// one digit's output range, so the stores coalesce.  offs is the scanned
+// digit-major histogram; the tile's own count of digit d is the difference
+// of two neighbouring entries.
 template <class K>
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uint32_t *vin, K *kout,
                                                          uint32_t *vout, uint32_t count, int shift,
                                                          const uint32_t *offs, uint32_t nblocks) {
-  __shared__ uint32_t base[256];
+  __shared__ K sk[RS_TILE];
+  __shared__ uint32_t sv[RS_TILE];
+  __shared__ uint32_t gbase[256];   // output position of the tile's first element of digit d
+  __shared__ uint32_t lstart[256];  // first LDS slot of digit d
+  __shared__ uint32_t lnext[256];   // next free LDS slot of digit d
   __shared__ uint32_t wcnt[RS_WAVES][256];
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  base[threadIdx.x] = offs[threadIdx.x * nblocks + blockIdx.x];
+  const int lane = __lane_id(), w = threadIdx.x >> 6, t = threadIdx.x;
+  const uint32_t b = blockIdx.x;
+  const uint32_t hidx = (uint32_t)t * nblocks + b;
+  const uint32_t g0 = offs[hidx];
+  gbase[t] = g0;
+  // exclusive scan of the tile's digit counts (256 threads, one per digit)
+  uint32_t c = offs[hidx + 1] - g0;
+  lstart[t] = c;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    const uint32_t add = t >= d ? lstart[t - d] : 0u;
+    __syncthreads();
+    lstart[t] += add;
+    __syncthreads();
+  }
+  const uint32_t ls = lstart[t] - c;  // exclusive
+  __syncthreads();
+  lstart[t] = ls;
+  lnext[t] = ls;
   const unsigned long long below = (1ull << lane) - 1ull;
-  const uint32_t tile = blockIdx.x * RS_TILE;
+  const uint32_t tile = b * RS_TILE;
   for (int r = 0; r < RS_ITEMS; ++r) {
-    const uint32_t e = tile + r * RS_BLOCK + threadIdx.x;
+    const uint32_t e = tile + r * RS_BLOCK + t;
     const bool valid = e < count;
     K key = 0;
     uint32_t val = 0, d = 0;
@@ -56,28 +84,36 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uin
     // lanes of this wave holding the same digit
     unsigned long long m = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const unsigned long long bb = __ballot(valid && bit);
-      m &= bit ? bb : ~bb;
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long bb = __ballot(valid && on);
+      m &= on ? bb : ~bb;
     }
 #pragma unroll
-    for (int k = 0; k < RS_WAVES; ++k) wcnt[k][threadIdx.x] = 0;
+    for (int k = 0; k < RS_WAVES; ++k) wcnt[k][t] = 0;
     __syncthreads();
     if (valid && lane == __ffsll((long long)m) - 1) wcnt[w][d] = (uint32_t)__popcll(m);
     __syncthreads();
     if (valid) {
-      uint32_t pos = base[d] + (uint32_t)__popcll(m & below);
+      uint32_t pos = lnext[d] + (uint32_t)__popcll(m & below);
       for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-      kout[pos] = key;
-      vout[pos] = val;
+      sk[pos] = key;
+      sv[pos] = val;
     }
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
-    for (int k = 0; k < RS_WAVES; ++k) add += wcnt[k][threadIdx.x];
-    base[threadIdx.x] += add;
+    for (int k = 0; k < RS_WAVES; ++k) add += wcnt[k][t];
+    lnext[t] += add;
     __syncthreads();
+  }
+  const uint32_t n_tile = min((uint32_t)RS_TILE, count - tile);
+  for (uint32_t j = t; j < n_tile; j += RS_BLOCK) {
+    const K key = sk[j];
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint32_t pos = gbase[d] + (j - lstart[d]);
+    kout[pos] = key;
+    vout[pos] = sv[j];
   }
 }
 
