@@ -271,7 +271,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
     HIP_OR_FAIL(launch_iota(vals, K, s));
     HIP_OR_FAIL(launch_radix_sort(fd.dtype == 0 ? 4 : 8, keys, vals, keys_tmp, vals_tmp, K, hist,
                                   stmp, scan_tmp_words((uint32_t)(hw - 1)), s));
-    HIP_OR_FAIL(launch_cp_init(fd, vals, ctx->d_comp, s));
+    HIP_OR_FAIL(launch_cp_init(fd, vals, (uint32_t *)keys_tmp, s));
   }
   return EXZ_OK;
 }

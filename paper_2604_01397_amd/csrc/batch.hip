@@ -525,7 +525,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
                                         b + ob[k][6], (uint32_t *)(b + ob[k][8]), K,
                                         (uint32_t *)(b + ob[k][9]), (uint32_t *)(b + ob[k][10]),
                                         scan_tmp_words((uint32_t)(hw - 1)), s));
-        HIP_OR_FAIL_B(launch_cp_init(fd, (uint32_t *)(b + ob[k][7]), ctx->d_comp, s));
+        HIP_OR_FAIL_B(launch_cp_init(fd, (uint32_t *)(b + ob[k][7]), (uint32_t *)(b + ob[k][6]), s));
       }
       host_fd[k] = fd;
     }

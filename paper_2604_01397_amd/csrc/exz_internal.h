@@ -94,7 +94,8 @@ struct FieldDev {
   uint32_t *succ;       // n: SUCC_SLOT bits: vertex-order slot of the next critical point
                         // of f in f's order, SUCC_BELOW: its index is below this one's;
                         // NONE for the last critical point and for other vertices
-  uint32_t *pred_box;   // n: box holding the previous critical point of f, NONE otherwise
+  uint32_t *pred_box;   // n: for a critical point of f, the box holding the previous one in
+                        // f's order (NONE for the first); undefined for other vertices
   void *cpv;            // K: current value of every critical point of f, in vertex order
   uint32_t *cp_idx;     // K, rank -> vertex
   uint32_t *sad_rank;   // saddle order -> rank in the CP order (K capacity)
@@ -267,7 +268,8 @@ hipError_t launch_radix_sort(int key_bytes, void *keys, uint32_t *vals, void *ke
                              uint32_t *vals_tmp, uint32_t count, uint32_t *hist, uint32_t *scan_tmp,
                              size_t scan_words, hipStream_t s);
 size_t radix_hist_words(uint32_t count);
-hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, const uint8_t *comp,
+// box_r: K words of scratch (the sort's spare key buffer serves).
+hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, uint32_t *box_r,
                           hipStream_t s);
 bool box_supported(int tile_y, int tile_z);
 hipError_t launch_state_reset(const FieldDev &fd, int64_t max_iters, hipStream_t s);

@@ -443,7 +443,9 @@ __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, ui
     if (fd.mode != 1 && ((d.cpm >> c) & 1u))
       glob((T *)fd.cpv)[d.vo0 + (uint32_t)__popc(d.cpm & ((1u << c) - 1u))] = nv;
     // the previous critical point in f's order compares itself with t
-    if (fd.frontier && d.pb[c] != NONE) glob(fd.bdirty)[d.pb[c]] = 1;
+    // (frontier passes run with the reformulated constraints, so cpm is set;
+    // pred_box is defined for critical points only)
+    if (fd.frontier && ((d.cpm >> c) & 1u) && d.pb[c] != NONE) glob(fd.bdirty)[d.pb[c]] = 1;
     moved |= 1u << c;
     ++ec.v[1];
     ec.v[3] += nv == L;

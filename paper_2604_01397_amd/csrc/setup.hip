@@ -123,7 +123,6 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd, const uint8_
     fd.code[i] = (uint8_t)(asc | (desc << 4));
     fd.low[i] = (uint16_t)low;
     fd.succ[i] = NONE;
-    fd.pred_box[i] = NONE;
     if (fd.g != fd.g_hat) ((T *)fd.g)[i] = gi;
     if (!fd.resume) fd.cnt[i] = 0;
   }
@@ -294,8 +293,9 @@ __device__ __forceinline__ uint32_t box_index(const FieldDev &fd, uint32_t v) {
 // After the stable sort of the keys (payload = vertex-order slot): the
 // rank -> vertex map, each critical point's successor in f's order (its
 // slot, and whether its vertex index is the lower one: slots follow vertex
-// order) and the box of its predecessor.
-__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint32_t *sorted_vo) {
+// order) and, for frontier passes, each rank's box in box_r.
+__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint32_t *sorted_vo,
+                                                         uint32_t *box_r) {
   const uint32_t r = blockIdx.x * SETUP_BLOCK + threadIdx.x;
   const uint32_t K = (uint32_t)fd.K;
   if (r >= K) return;
@@ -308,14 +308,23 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint
   } else {
     fd.succ[v] = NONE;
   }
-  fd.pred_box[v] = r > 0 ? box_index(fd, fd.cp_vtx[sorted_vo[r - 1]]) : NONE;
+  if (fd.frontier) box_r[r] = box_index(fd, v);
 }
 
-hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, const uint8_t *,
+// Frontier passes: every critical point learns the box of its predecessor
+// (read in rank order, so only the store is scattered).
+__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_pred(FieldDev fd, const uint32_t *box_r) {
+  const uint32_t r = blockIdx.x * SETUP_BLOCK + threadIdx.x;
+  if (r >= (uint32_t)fd.K) return;
+  fd.pred_box[fd.cp_idx[r]] = r > 0 ? box_r[r - 1] : NONE;
+}
+
+hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, uint32_t *box_r,
                           hipStream_t s) {
   if (fd.K == 0) return hipSuccess;
   const int grid = (fd.K + SETUP_BLOCK - 1) / SETUP_BLOCK;
-  hipLaunchKernelGGL(k_cp_init, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
+  hipLaunchKernelGGL(k_cp_init, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo, box_r);
+  if (fd.frontier) hipLaunchKernelGGL(k_cp_pred, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, box_r);
   return hipGetLastError();
 }
 
