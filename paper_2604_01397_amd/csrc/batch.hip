@@ -67,8 +67,8 @@ __global__ void __launch_bounds__(64 * TY)
     bool take = !st->done;
     if (take && fd.frontier && !st->dense) take = fd.bdirty[tile] != 0;
     if (take) {
-      if (fd.frontier && !st->dense) {
-        __syncthreads();  // every thread has read the flag
+      if (fd.frontier) {
+        __syncthreads();  // every thread has read the flag (frontier pass)
         if (threadIdx.x == 0 && threadIdx.y == 0) fd.bdirty[tile] = 0;
       }
       check_box<T, TY, TZ>(fd, box_of(fd, tile, TY, TZ), L);

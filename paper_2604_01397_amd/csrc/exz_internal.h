@@ -49,6 +49,7 @@ struct State {
   uint32_t shard[5][64];  // per-iteration counters of the apply pass, sharded by block
   uint32_t nsaddle;       // saddles of f (original mode)
   int32_t dense;          // the next check covers every box (first pass, fixpoint confirmation)
+  int32_t noflag;         // this iteration's apply sets no box flags (the next check is dense)
   uint32_t jump[MAX_JUMP_ROUNDS];  // pointer-jumping round flags
   int64_t iterations;
   int64_t edit_ops;

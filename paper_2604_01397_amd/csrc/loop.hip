@@ -67,10 +67,14 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
   uint32_t done_v = 0;  // vertices checked by this work-group (lead thread)
   if (!fd.frontier || st->dense) {
+    // a dense pass consumes every box flag: clear them, so none is stale
     for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
       const BoxOrigin o = box_of(fd, tile, TY, TZ);
       check_box<T, TY, TZ>(fd, o, L);
-      if (lead) done_v += box_vertices(fd, o, TY, TZ);
+      if (lead) {
+        done_v += box_vertices(fd, o, TY, TZ);
+        if (fd.frontier) fd.bdirty[tile] = 0;
+      }
       __syncthreads();
     }
   } else {
@@ -129,6 +133,7 @@ __global__ void __launch_bounds__(64) k_state_reset(State *st, int64_t max_iters
   st->cert_bad = 0;
   st->nsaddle = 0;
   st->dense = 1;
+  st->noflag = 1;  // the first iterations change values in nearly every box
   st->iterations = st->edit_ops = st->lossless_total = st->floor_total = st->edited_total = 0;
   st->residual = 0;
   st->max_iters = max_iters;

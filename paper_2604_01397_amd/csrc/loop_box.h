@@ -371,9 +371,11 @@ struct QuadIn {
 
 // Loads the inputs of the quad at v whose mark bytes are m (m != 0): vector
 // loads when the whole quad is in the field and aligned, else one load per
-// vertex (unmarked ones read vertex v, which is valid).
+// vertex (unmarked ones read vertex v, which is valid).  flag: this apply
+// sets the box flags of the next frontier pass.
 template <class T>
-__device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32_t m, QuadIn<T> &d) {
+__device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32_t m, bool flag,
+                                          QuadIn<T> &d) {
   const T *G = (const T *)fd.g;
   const T *F = (const T *)fd.f;
   if (fd.vec && v + 3 < (uint32_t)fd.n) {
@@ -382,7 +384,7 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32
     const uint32_t c4 = *glob(reinterpret_cast<const uint32_t *>(fd.cnt + v));
 #pragma unroll
     for (int c = 0; c < 4; ++c) d.c[c] = (c4 >> (8 * c)) & 255u;
-    if (fd.frontier) {
+    if (flag) {
       const u32x4 p4 = *glob(reinterpret_cast<const u32x4 *>(fd.pred_box + v));
       d.pb[0] = p4.x;
       d.pb[1] = p4.y;
@@ -396,7 +398,7 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32
       d.g[c] = glob(G)[t];
       d.f[c] = glob(F)[t];
       d.c[c] = glob(fd.cnt)[t];
-      if (fd.frontier) d.pb[c] = glob(fd.pred_box)[t];
+      if (flag) d.pb[c] = glob(fd.pred_box)[t];
     }
   }
   if (fd.mode != 1) {  // a quad lies in one 64-vertex chunk of the bitmask
@@ -413,7 +415,7 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32
 // and one 32-bit store of its counts (unmarked vertices keep theirs).
 // Returns the vertices whose value or count moved, as bits 0..3.
 template <class T>
-__device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, uint32_t m,
+__device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, uint32_t m, bool flag,
                                               const QuadIn<T> &d, EditCount &ec) {
   T *G = (T *)fd.g;
   const T xiT = (T)fd.xiT, delta = (T)fd.delta;
@@ -445,7 +447,7 @@ __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, ui
     // the previous critical point in f's order compares itself with t
     // (frontier passes run with the reformulated constraints, so cpm is set;
     // pred_box is defined for critical points only)
-    if (fd.frontier && ((d.cpm >> c) & 1u) && d.pb[c] != NONE) glob(fd.bdirty)[d.pb[c]] = 1;
+    if (flag && ((d.cpm >> c) & 1u) && d.pb[c] != NONE) glob(fd.bdirty)[d.pb[c]] = 1;
     moved |= 1u << c;
     ++ec.v[1];
     ec.v[3] += nv == L;
@@ -494,10 +496,13 @@ __device__ __forceinline__ void mark_moved_boxes(const FieldDev &fd, uint32_t v,
 // ApplyBoundedEdits over quads q = q0, q0 + stride, ... (< nq): the marks
 // of the next quad are fetched before the current one is edited.  One quad
 // per thread at a time keeps the register count, and so the number of waves
-// in flight, high.
+// in flight, high.  Box flags for the next frontier pass are set unless the
+// last pass changed so many values that the next check covers every box
+// anyway (State::noflag).
 template <class T>
 __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uint32_t stride,
                                             uint32_t nq, EditCount &ec) {
+  const bool flag = fd.frontier && !fd.st->noflag;
   uint32_t m = q0 < nq ? quad_marks(fd, q0) : 0u;
   for (uint32_t q = q0; q < nq; q += stride) {
     const uint32_t qn = q + stride;
@@ -505,10 +510,10 @@ __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uin
     uint32_t moved = 0;
     if (m) {
       QuadIn<T> d;
-      load_quad<T>(fd, 4u * q, m, d);
-      moved = edit_quad<T>(fd, 4u * q, m, d, ec);
+      load_quad<T>(fd, 4u * q, m, flag, d);
+      moved = edit_quad<T>(fd, 4u * q, m, flag, d, ec);
     }
-    if (fd.frontier) mark_moved_boxes(fd, 4u * q, moved);
+    if (flag) mark_moved_boxes(fd, 4u * q, moved);
     m = mn;
   }
 }
@@ -530,6 +535,8 @@ __device__ __forceinline__ void flush_counts(State *st, EditCount ec, uint32_t s
     if (v) atomicAdd(&st->shard[tid][shard & 63u], v);
   }
 }
+
+constexpr uint32_t NOFLAG_PER_BOX = 4;
 
 // Sums the shards of the apply pass and decides how the loop goes on.
 __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
@@ -555,13 +562,18 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
     // cannot tell a fixpoint from convergence (or count the residual): dense
     // passes over the unchanged field settle it.
     st->dense = 1;
+    st->noflag = 0;
   } else if (nt == 0) {
     st->done = CONVERGED;
   } else if (ch == 0) {
     st->done = STUCK;
     st->residual = nt;
   } else {
-    st->dense = 0;
+    // an apply that set no box flags is followed by a check of every box;
+    // after many changes (more than NOFLAG_PER_BOX per box) nearly every box
+    // would be flagged, so the next apply skips the flags
+    st->dense = st->noflag;
+    st->noflag = fd.frontier && ch > NOFLAG_PER_BOX * (uint32_t)fd.ntiles;
     st->iterations += 1;
     st->edit_ops += ch;
     st->lossless_total += v[2];
