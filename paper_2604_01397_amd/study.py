@@ -7,7 +7,11 @@
              Sec. 5.4);
 --nsweep     N = 1 .. 10 at one bound: time, iterations, edited vertices,
              lossless edits and edit-stream size (App. C: fewer steps mean
-             fewer iterations and more lossless edits).
+             fewer iterations and more lossless edits);
+--table1     the Table 1 analogue (Sec. 4.4): vertices in the weak, strong
+             and reduced vulnerability graphs, edited vertices, the
+             iteration bound from D_max(G_R) and the actual iterations, for
+             the 128^3, 256^3 and 512^3 GRF fields at bound 1e-4.
 
 Input: the 3D float32 GRF k^-11/3 of the 512^3 workload (seed 2, or an
 --edge^3 version), Lorenzo quantiser at each bound.  The edit stream is
@@ -48,16 +52,62 @@ def run_one(ctx, exactz, editcodec, torch, f_host, g_host, f, g, xi, mode, n_ste
             "stream": len(es.data), "zlib": es.compressed(1), "exact": es.exact}
 
 
+def table1(torch, exactz, synth, edges=(128, 256, 512), rel=1e-4, n_steps=5):
+    from . import vulnerability
+    print("### Vulnerability graphs vs actual iterations, rel. bound %g, N = %d\n" % (rel, n_steps))
+    print("| field | \\|G_V\\| % | \\|G_S\\| % | \\|G_R\\| % | edit % | D_max(G_R) | "
+          "bound (N+1)·D_max | N·D_max | actual iterations | analysis s |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|")
+    fields = [("128^3 GRF k^-3, uniform", 128, -3.0, 1, "uniform"),
+              ("256^3 GRF k^-11/3, Lorenzo", 256, -11.0 / 3.0, 2, "lorenzo"),
+              ("512^3 GRF k^-11/3, Lorenzo", 512, -11.0 / 3.0, 2, "lorenzo")]
+    ctx = exactz.Context(0)
+    try:
+        for name, edge, slope, seed, q in fields:
+            if edge not in edges:
+                continue
+            fh = synth.grf3d(edge, seed=seed, slope=slope)
+            log("%s: generated" % name)
+            xi = synth.eps_for(fh, rel)
+            gh = synth.quantize_lorenzo(fh, xi) if q == "lorenzo" else synth.quantize_uniform(fh, xi)
+            f = torch.from_numpy(fh).cuda()
+            g = torch.from_numpy(gh).cuda()
+            _, _, r = ctx.correct(f, g, xi, n_steps=n_steps)
+            torch.cuda.synchronize()
+            log("%s: corrected (%d iterations)" % (name, r["iterations"]))
+            t0 = time.perf_counter()
+            m = vulnerability.metrics(f.view(-1), g.view(-1), xi, (edge, edge, edge))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            n = fh.size
+            log("%s: %s, result %s" % (name, m, r))
+            print("| %s | %.2f | %.2f | %.2f | %.2f | %d | %d | %d | %d | %.1f |" % (
+                name, 100.0 * m["V_GV"] / n, 100.0 * m["V_GS"] / n, 100.0 * m["V_GR"] / n,
+                100.0 * r["edited_vertices"] / n, m["D_max"], (n_steps + 1) * m["D_max"],
+                n_steps * m["D_max"], r["iterations"], dt))
+            del f, g
+            torch.cuda.empty_cache()
+    finally:
+        ctx.close()
+    print()
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--edge", type=int, default=512)
     ap.add_argument("--tradeoff", action="store_true")
     ap.add_argument("--nsweep", action="store_true")
     ap.add_argument("--rel", type=float, default=1e-4, help="bound of the N sweep")
+    ap.add_argument("--table1", action="store_true")
+    ap.add_argument("--table1-edges", type=int, nargs="*", default=[128, 256, 512])
     a = ap.parse_args(argv)
     import torch
 
     from . import editcodec, exactz, synth
+    if a.table1:
+        table1(torch, exactz, synth, edges=tuple(a.table1_edges))
+        if not (a.tradeoff or a.nsweep):
+            return 0
     t0 = time.time()
     f_host = synth.grf3d(a.edge, seed=2, slope=-11.0 / 3.0)
     log("field %d^3 in %.1f s" % (a.edge, time.time() - t0))
