@@ -239,7 +239,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   uint32_t *scan_tmp = (uint32_t *)(base + oa[7]);
 
   HIP_OR_FAIL(launch_state_reset(fd, max_iters, s));
-  HIP_OR_FAIL(launch_setup(fd, ctx->d_comp, s));
+  HIP_OR_FAIL(launch_setup(fd, ctx->d_conn, s));
   HIP_OR_FAIL(launch_scan_u32(fd.cpoff, fd.cpoff, (uint32_t)fd.nchunk, scan_tmp,
                               scan_tmp_words((uint32_t)fd.nchunk), s));
   HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));

@@ -469,7 +469,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.vec = quad_aligned(fd);
       uint32_t *scan_tmp = (uint32_t *)(b + oa[k][7]);
       HIP_OR_FAIL_B(launch_state_reset(fd, mem[k].max_iters, s));
-      HIP_OR_FAIL_B(launch_setup(fd, ctx->d_comp, s));
+      HIP_OR_FAIL_B(launch_setup(fd, ctx->d_conn, s));
       HIP_OR_FAIL_B(launch_scan_u32(fd.cpoff, fd.cpoff, (uint32_t)fd.nchunk, scan_tmp,
                                     scan_tmp_words((uint32_t)fd.nchunk), s));
     }

@@ -260,7 +260,10 @@ void build_component_table(uint8_t *out16k);
 void build_connected_bits(const uint8_t *comp16k, uint32_t *out512);
 
 // Launch wrappers (kernels live in setup.hip / loop.hip / sort.hip).
-hipError_t launch_setup(const FieldDev &fd, const uint8_t *comp, hipStream_t s);
+// Reference topology of f (code, low) box by box; conn = one-component bits.
+hipError_t launch_ref(const FieldDev &fd, const uint32_t *conn, hipStream_t s);
+// launch_ref, then validation, copies and the critical-point bitmask.
+hipError_t launch_setup(const FieldDev &fd, const uint32_t *conn, hipStream_t s);
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, uint32_t count, uint32_t *tmp,
                            size_t tmp_words, hipStream_t s);
 size_t scan_tmp_words(uint32_t count);

@@ -110,6 +110,18 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
 }
 
+// Reference topology of f, box by box over the same persistent walk.
+template <class T, int TY, int TZ>
+__global__ void __launch_bounds__(64 * TY) k_ref(FieldDev fd, const uint32_t *__restrict__ conn) {
+  __shared__ RefLds<T, TY, TZ> L;
+  copy_conn<TY>(L.conn, conn);
+  const BoxWalk w = box_walk(fd);
+  for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
+    ref_box<T, TY, TZ>(fd, box_of(fd, tile, TY, TZ), L);
+    __syncthreads();
+  }
+}
+
 // ApplyBoundedEdits over the target marks.
 template <class T>
 __global__ void __launch_bounds__(APPLY_BLOCK) k_apply(FieldDev fd) {
@@ -175,6 +187,23 @@ static void launch_check_events(const FieldDev &fd, const uint32_t *conn, const 
 #undef EXZ_BOX_CHECK
   if (ev1) (void)hipEventRecord(ev1, s);
   if (fd.mode == 1) (void)launch_original_events(fd, comp, s);
+}
+
+template <class T>
+static void launch_ref_t(const FieldDev &fd, const uint32_t *conn, hipStream_t s) {
+#define EXZ_BOX_REF(a, b)                                                                  \
+  if (fd.tile_y == a && fd.tile_z == b)                                                    \
+    hipLaunchKernelGGL((k_ref<T, a, b>), dim3(persistent_grid(fd)), dim3(64, a), 0, s, fd, conn);
+  EXZ_BOX_SHAPES(EXZ_BOX_REF)
+#undef EXZ_BOX_REF
+}
+
+hipError_t launch_ref(const FieldDev &fd, const uint32_t *conn, hipStream_t s) {
+  if (fd.dtype == 0)
+    launch_ref_t<float>(fd, conn, s);
+  else
+    launch_ref_t<double>(fd, conn, s);
+  return hipGetLastError();
 }
 
 template <class T>

@@ -99,22 +99,19 @@ __device__ __forceinline__ void stage_rows(const FieldDev &fd, const V *__restri
   }
 }
 
-// Requests of one vertex as a slot mask (bit SELF = the vertex itself).
+// Order of a vertex within its closed neighbourhood, from staged values
+// (cells outside the domain are NaN): the slots of the SoS maximum and
+// minimum (SELF for the vertex itself) and the mask of lower neighbours.
 // P points at the LDS centre value of the vertex; pm / pp are the offsets
-// of the planes below / above relative to the centre plane; dlt holds the
-// linear offset of every slot.
+// of the planes below / above relative to the centre plane.
 template <class T>
-__device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint32_t *__restrict__ conn,
-                                                 const int32_t *dlt, const T *P, int pm, int pp,
-                                                 int x, int y, int z,
-                                                 uint32_t i, uint32_t codeb, uint32_t lowf,
-                                                 uint32_t &asc_v, uint32_t &desc_v, bool interior) {
+__device__ __forceinline__ void closed_order(const T *P, int pm, int pp, int &asc, int &desc,
+                                             uint32_t &lower) {
   // Vertex indices of the neighbours, ascending: the slots with a negative
   // offset (odd), the vertex itself, the slots with a positive offset (even).
   // Offsets are dx + nx*dy + nx*ny*dz, ordered lexicographically by
   // (dz, dy, dx) on any grid where the slot is in the domain.
   constexpr int ORDER[NSLOT + 1] = {13, 11, 9, 7, 5, 3, 1, SELF, 0, 2, 4, 6, 8, 10, 12};
-  const uint32_t vm = interior ? 0x3FFFu : slots_in_domain(x, y, z, fd.nx, fd.ny, fd.nz);
   T v[NSLOT + 1];  // closed neighbourhood in index order
 #pragma unroll
   for (int q = 0; q <= NSLOT; ++q) {
@@ -134,7 +131,8 @@ __device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint3
     hi = fmax(hi, v[q]);
     lo = fmin(lo, v[q]);
   }
-  int asc = SELF, desc = SELF;
+  asc = SELF;
+  desc = SELF;
 #pragma unroll
   for (int q = 0; q <= NSLOT; ++q) {
     asc = v[q] == hi ? ORDER[q] : asc;
@@ -142,12 +140,28 @@ __device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint3
   }
   // A neighbour with a lower index is below i when its value is <= g_i,
   // one with a higher index when it is < g_i; NaN never compares true.
-  uint32_t lower = 0;
+  lower = 0;
 #pragma unroll
   for (int q = 0; q <= NSLOT; ++q) {
     if (q == 7) continue;
     lower |= (uint32_t)(q < 7 ? v[q] <= gi : v[q] < gi) << ORDER[q];
   }
+}
+
+// Requests of one vertex as a slot mask (bit SELF = the vertex itself).
+// P points at the LDS centre value of the vertex; pm / pp are the offsets
+// of the planes below / above relative to the centre plane; dlt holds the
+// linear offset of every slot.
+template <class T>
+__device__ __forceinline__ uint32_t check_vertex(const FieldDev &fd, const uint32_t *__restrict__ conn,
+                                                 const int32_t *dlt, const T *P, int pm, int pp,
+                                                 int x, int y, int z,
+                                                 uint32_t i, uint32_t codeb, uint32_t lowf,
+                                                 uint32_t &asc_v, uint32_t &desc_v, bool interior) {
+  const uint32_t vm = interior ? 0x3FFFu : slots_in_domain(x, y, z, fd.nx, fd.ny, fd.nz);
+  int asc, desc;
+  uint32_t lower;
+  closed_order<T>(P, pm, pp, asc, desc, lower);
   if (fd.mode == 1) {  // vertex indices are needed for path tracing only
     asc_v = (uint32_t)((int)i + dlt[asc]);
     desc_v = (uint32_t)((int)i + dlt[desc]);
@@ -212,11 +226,64 @@ struct CheckLds {
   int32_t dlt[16];
 };
 
-// Copies the connectivity bits into LDS; the barrier of the first check_box
+// Copies the connectivity bits into LDS; the barrier of the first box
 // orders it before any use.
+template <int TY>
+__device__ __forceinline__ void copy_conn(uint32_t *dst, const uint32_t *__restrict__ conn) {
+  for (int k = threadIdx.y * 64 + threadIdx.x; k < CONN_WORDS; k += 64 * TY) dst[k] = conn[k];
+}
 template <class T, int TY, int TZ>
 __device__ __forceinline__ void load_conn(CheckLds<T, TY, TZ> &L, const uint32_t *__restrict__ conn) {
-  for (int k = threadIdx.y * 64 + threadIdx.x; k < CONN_WORDS; k += 64 * TY) L.conn[k] = conn[k];
+  copy_conn<TY>(L.conn, conn);
+}
+
+__device__ __forceinline__ bool one_component(const uint32_t *conn, uint32_t m) {
+  return (conn[m >> 5] >> (m & 31u)) & 1u;
+}
+
+// LDS of one reference-topology work-group: the staged box of f and the
+// link connectivity bits.
+template <class T, int TY, int TZ>
+struct RefLds {
+  T S[Box<TY, TZ>::NE];
+  uint32_t conn[CONN_WORDS];
+};
+
+// Reference topology of f on one box (Sec. 3.1-3.2): per vertex the code
+// byte (steepest ascent slot | steepest descent slot << 4, SELF at a maximum
+// / minimum) and the lower mask, with LOW_SADDLE when the lower or the upper
+// link is not one connected piece.  The caller synchronises the block after
+// it.
+template <class T, int TY, int TZ>
+__device__ __forceinline__ void ref_box(const FieldDev &fd, BoxOrigin o, RefLds<T, TY, TZ> &L) {
+  using B = Box<TY, TZ>;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x = o.x0 + lx, y = o.y0 + ly;
+  const bool col = x < fd.nx && y < fd.ny;
+  const uint32_t plane = (uint32_t)fd.nx * (uint32_t)fd.ny;
+  const uint32_t i0 = (uint32_t)x + (uint32_t)fd.nx * ((uint32_t)y + (uint32_t)fd.ny * (uint32_t)o.z0);
+  stage_rows<TY, TZ>(fd, (const T *)fd.f, L.S, o);
+  const bool interior = o.x0 >= 1 && o.x0 + 64 <= fd.nx - 1 && o.y0 >= 1 &&
+                        o.y0 + TY <= fd.ny - 1 && o.z0 >= 1 && o.z0 + TZ <= fd.nz - 1;
+  __syncthreads();
+#pragma unroll 1
+  for (int k = 0; k < TZ; ++k) {
+    const int z = o.z0 + k;
+    if (col && z < fd.nz) {
+      const uint32_t i = i0 + k * plane;
+      const T *c = L.S + (k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1;
+      const uint32_t vm = interior ? 0x3FFFu : slots_in_domain(x, y, z, fd.nx, fd.ny, fd.nz);
+      int asc, desc;
+      uint32_t lower;
+      closed_order<T>(c, -B::PLANE, B::PLANE, asc, desc, lower);
+      uint32_t low = lower;
+      if (lower != 0 && lower != vm &&
+          !(one_component(L.conn, lower) && one_component(L.conn, vm & ~lower)))
+        low |= LOW_SADDLE;
+      glob(fd.code)[i] = (uint8_t)(asc | (desc << 4));
+      glob(fd.low)[i] = (uint16_t)low;
+    }
+  }
 }
 
 // CheckConstraints on one box: stage g (and the box's reference codes), add

@@ -57,52 +57,13 @@ void build_connected_bits(const uint8_t *comp, uint32_t *out) {
 constexpr int SETUP_BLOCK = 256;
 
 template <class T>
-__device__ __forceinline__ void local_f(const T *F, uint32_t i, int x, int y, int z,
-                                        const FieldDev &fd, uint32_t &vm, uint32_t &lower,
-                                        int &asc, int &desc) {
-  vm = valid_slots(x, y, z, fd.nx, fd.ny, fd.nz);
-  const int nxy = fd.nx * fd.ny;
-  const T fi = F[i];
-  T amax = fi, amin = fi;
-  uint32_t ia = i, id = i;
-  asc = SELF;
-  desc = SELF;
-  lower = 0;
-  T fn[NSLOT];
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const bool ok = (vm >> s) & 1u;
-    fn[s] = F[ok ? (uint32_t)((int)i + slot_delta(s, fd.nx, nxy)) : i];
-  }
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const bool ok = (vm >> s) & 1u;
-    const uint32_t j = (uint32_t)((int)i + slot_delta(s, fd.nx, nxy));
-    const T fj = fn[s];
-    lower |= (uint32_t)(ok & sos_lt(fj, j, fi, i)) << s;
-    const bool up = ok & sos_lt(amax, ia, fj, j);
-    amax = up ? fj : amax;
-    ia = up ? j : ia;
-    asc = up ? s : asc;
-    const bool dn = ok & sos_lt(fj, j, amin, id);
-    amin = dn ? fj : amin;
-    id = dn ? j : id;
-    desc = dn ? s : desc;
-  }
-}
-
-template <class T>
-__global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd, const uint8_t *__restrict__ comp) {
+__global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd) {
   const uint32_t i = blockIdx.x * SETUP_BLOCK + threadIdx.x;
   const bool active = i < (uint32_t)fd.n;
   bool cp = false;
   if (active) {
     const T *F = (const T *)fd.f;
     const T *Gh = (const T *)fd.g_hat;
-    const int x = (int)(i % (uint32_t)fd.nx);
-    const uint32_t r = i / (uint32_t)fd.nx;
-    const int y = (int)(r % (uint32_t)fd.ny);
-    const int z = (int)(r / (uint32_t)fd.ny);
     const T fi = F[i], gi = Gh[i];
     if (!isfinite(fi) || !isfinite(gi)) {
       atomicOr(&fd.st->err, ERR_NONFINITE);
@@ -110,18 +71,10 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd, const uint8_
       const T xiT = (T)fd.xiT;
       if (gi < lower_bound(fi, xiT) || gi > upper_bound(fi, xiT)) atomicOr(&fd.st->err, ERR_BOUND);
     }
-    uint32_t vm, lower;
-    int asc, desc;
-    local_f(F, i, x, y, z, fd, vm, lower, asc, desc);
-    uint32_t low = lower;
-    if (lower == 0 || lower == vm) {
-      cp = true;  // minimum or maximum (a lone vertex counts as a minimum)
-    } else if (!(comp[lower] == 1 && comp[vm & ~lower] == 1)) {
-      cp = true;
-      low |= LOW_SADDLE;
-    }
-    fd.code[i] = (uint8_t)(asc | (desc << 4));
-    fd.low[i] = (uint16_t)low;
+    // a maximum is its own steepest ascent, a minimum its own steepest
+    // descent (a lone vertex counts as a minimum)
+    const uint32_t code = fd.code[i];
+    cp = (code & 15u) == SELF || (code >> 4) == SELF || (fd.low[i] & LOW_SADDLE);
     fd.succ[i] = NONE;
     if (fd.g != fd.g_hat) ((T *)fd.g)[i] = gi;
     if (!fd.resume) fd.cnt[i] = 0;
@@ -137,12 +90,16 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd, const uint8_
   }
 }
 
-hipError_t launch_setup(const FieldDev &fd, const uint8_t *comp, hipStream_t s) {
+// The reference topology box by box (staged through LDS), then validation,
+// copies and the critical-point bitmask from its codes.
+hipError_t launch_setup(const FieldDev &fd, const uint32_t *conn, hipStream_t s) {
+  const hipError_t e = launch_ref(fd, conn, s);
+  if (e != hipSuccess) return e;
   const int grid = (fd.n + SETUP_BLOCK - 1) / SETUP_BLOCK;
   if (fd.dtype == 0)
-    hipLaunchKernelGGL(k_setup<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, comp);
+    hipLaunchKernelGGL(k_setup<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd);
   else
-    hipLaunchKernelGGL(k_setup<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, comp);
+    hipLaunchKernelGGL(k_setup<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd);
   return hipGetLastError();
 }
 
