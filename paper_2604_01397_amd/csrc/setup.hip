@@ -1,6 +1,7 @@
-// Setup of one correction: validation of the band, reference topology of f
-// packed into one code byte per vertex, the critical-point bitmask, the
-// prefix counts that index it, the critical-point list and its sorted order.
+// Setup of one correction: validation of the band, the critical-point
+// bitmask (from f's reference topology, which k_ref in loop.hip computes
+// box by box with the check's own staging), the prefix counts that index
+// it, the critical-point list and its sorted order.
 //
 // Paper: steepest ascent/descent neighbours and critical types from local
 // comparisons (Sec. 3.1-3.2); the error band |f - g| <= xi (Sec. 4.1); the
