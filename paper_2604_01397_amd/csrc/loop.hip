@@ -10,8 +10,6 @@
 //   apply     ApplyBoundedEdits (Sec. 3.3): every marked vertex is edited in
 //             place and its mark cleared;
 //   finalize  convergence / stuck / iteration-cap decision, counter reset.
-// The reference topology of f (k_ref, run once at setup) uses the same box
-// walk, staging and closed-neighbourhood order as the check.
 // A mark is a plain store of 1: many checks may mark the same vertex, and
 // every such store leaves the same byte, so no atomics are needed.  All
 // checks of an iteration read the same g, and the edits run in a later

@@ -1,6 +1,7 @@
 // Setup of one correction: validation of the band, the critical-point
 // bitmask (from f's reference topology, which k_ref in loop.hip computes
-// box by box with the check's own staging), the prefix counts that index
+// box by box with the check's box walk, staging and closed-neighbourhood
+// order), the prefix counts that index
 // it, the critical-point list and its sorted order.
 //
 // Paper: steepest ascent/descent neighbours and critical types from local
