@@ -373,6 +373,10 @@ exz_status exz_ctx_destroy(exz_ctx *ctx) {
   if (ctx->order_in) (void)hipEventDestroy(ctx->order_in);
   if (ctx->order_out) (void)hipEventDestroy(ctx->order_out);
   if (ctx->work) (void)hipStreamDestroy(ctx->work);
+  for (int j = 0; j < exz_ctx::NSIDE; ++j)
+    if (ctx->side[j]) (void)hipStreamDestroy(ctx->side[j]);
+  for (int j = 0; j <= exz_ctx::NSIDE; ++j)
+    if (ctx->side_ev[j]) (void)hipEventDestroy(ctx->side_ev[j]);
   for (auto &e : ctx->events) (void)hipEventDestroy(e);
   if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
   if (ctx->ev_setup) (void)hipEventDestroy(ctx->ev_setup);

@@ -359,6 +359,36 @@ hipError_t ensure_work_stream(exz_ctx *ctx) {
   return hipEventCreateWithFlags(&ctx->order_out, hipEventDisableTiming);
 }
 
+// The side streams start after everything issued so far on s ...
+static hipError_t side_fork(exz_ctx *ctx, hipStream_t s) {
+  for (int j = 0; j < exz_ctx::NSIDE; ++j) {
+    if (!ctx->side[j]) {
+      const hipError_t e = hipStreamCreateWithFlags(&ctx->side[j], hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+  }
+  for (int j = 0; j <= exz_ctx::NSIDE; ++j) {
+    if (!ctx->side_ev[j]) {
+      const hipError_t e = hipEventCreateWithFlags(&ctx->side_ev[j], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipError_t e = hipEventRecord(ctx->side_ev[exz_ctx::NSIDE], s);
+  for (int j = 0; j < exz_ctx::NSIDE && e == hipSuccess; ++j)
+    e = hipStreamWaitEvent(ctx->side[j], ctx->side_ev[exz_ctx::NSIDE], 0);
+  return e;
+}
+
+// ... and s continues after everything issued on them.
+static hipError_t side_join(exz_ctx *ctx, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < exz_ctx::NSIDE && e == hipSuccess; ++j) {
+    e = hipEventRecord(ctx->side_ev[j], ctx->side[j]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->side_ev[j], 0);
+  }
+  return e;
+}
+
 }  // namespace exz
 
 extern "C" {
@@ -452,7 +482,11 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     State *states = (State *)(A + st_off);
     FieldDev *dev_fields = (FieldDev *)(A + fd_off);
     uint32_t *gather = (uint32_t *)(A + gather_off);
+    // fields are set up independently (own workspace), spread over the
+    // side streams so that their many small kernels overlap
+    HIP_OR_FAIL_B(side_fork(ctx, s));
     for (size_t k = 0; k < nb; ++k) {
+      hipStream_t sk = ctx->side[k % exz_ctx::NSIDE];
       FieldDev &fd = mem[k].fd;
       char *b = A + baseA[k];
       fd.st = states + k;
@@ -468,11 +502,12 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.cnt = cnt_io ? cnt_io : (uint8_t *)(b + oa[k][6]);
       fd.vec = quad_aligned(fd);
       uint32_t *scan_tmp = (uint32_t *)(b + oa[k][7]);
-      HIP_OR_FAIL_B(launch_state_reset(fd, mem[k].max_iters, s));
-      HIP_OR_FAIL_B(launch_setup(fd, ctx->d_conn, s));
+      HIP_OR_FAIL_B(launch_state_reset(fd, mem[k].max_iters, sk));
+      HIP_OR_FAIL_B(launch_setup(fd, ctx->d_conn, sk));
       HIP_OR_FAIL_B(launch_scan_u32(fd.cpoff, fd.cpoff, (uint32_t)fd.nchunk, scan_tmp,
-                                    scan_tmp_words((uint32_t)fd.nchunk), s));
+                                    scan_tmp_words((uint32_t)fd.nchunk), sk));
     }
+    HIP_OR_FAIL_B(side_join(ctx, s));
     std::vector<FieldDev> host_fd(nb);
     for (size_t k = 0; k < nb; ++k) host_fd[k] = mem[k].fd;
     HIP_OR_FAIL_B(hipMemcpyAsync(dev_fields, host_fd.data(), nb * sizeof(FieldDev),
@@ -508,8 +543,10 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     }
     HIP_OR_FAIL_B(ctx->BB.reserve(LB.total ? LB.total : 256));
     char *Bm = (char *)ctx->BB.take(LB.total);
+    HIP_OR_FAIL_B(side_fork(ctx, s));
     for (size_t k = 0; k < nb; ++k) {
       Member &m = mem[k];
+      hipStream_t sk = ctx->side[k % exz_ctx::NSIDE];
       if (!m.active) continue;
       FieldDev &fd = m.fd;
       char *b = Bm + baseB[k];
@@ -519,16 +556,17 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       const uint32_t K = (uint32_t)fd.K;
       if (K > 0) {
         const size_t hw = radix_hist_words(K);
-        HIP_OR_FAIL_B(launch_cp_compact(fd, ctx->d_comp, b + ob[k][5], s));
-        HIP_OR_FAIL_B(launch_iota((uint32_t *)(b + ob[k][7]), K, s));
+        HIP_OR_FAIL_B(launch_cp_compact(fd, ctx->d_comp, b + ob[k][5], sk));
+        HIP_OR_FAIL_B(launch_iota((uint32_t *)(b + ob[k][7]), K, sk));
         HIP_OR_FAIL_B(launch_radix_sort(fd.dtype == 0 ? 4 : 8, b + ob[k][5], (uint32_t *)(b + ob[k][7]),
                                         b + ob[k][6], (uint32_t *)(b + ob[k][8]), K,
                                         (uint32_t *)(b + ob[k][9]), (uint32_t *)(b + ob[k][10]),
-                                        scan_tmp_words((uint32_t)(hw - 1)), s));
-        HIP_OR_FAIL_B(launch_cp_init(fd, (uint32_t *)(b + ob[k][7]), (uint32_t *)(b + ob[k][6]), s));
+                                        scan_tmp_words((uint32_t)(hw - 1)), sk));
+        HIP_OR_FAIL_B(launch_cp_init(fd, (uint32_t *)(b + ob[k][7]), (uint32_t *)(b + ob[k][6]), sk));
       }
       host_fd[k] = fd;
     }
+    HIP_OR_FAIL_B(side_join(ctx, s));
     HIP_OR_FAIL_B(hipMemcpyAsync(dev_fields, host_fd.data(), nb * sizeof(FieldDev),
                                  hipMemcpyHostToDevice, s));
     HIP_OR_FAIL_B(hipEventRecord(e1, s));

@@ -80,6 +80,12 @@ struct exz_ctx {
   size_t step_cap = 0;
   hipEvent_t step_copied = nullptr;
   hipStream_t work = nullptr;       // internal stream for captured work (default priority)
+  // streams (default priority) over which the batched set-up of independent
+  // fields is spread, and the events that fork them from / join them to the
+  // caller's stream
+  static constexpr int NSIDE = 4;
+  hipStream_t side[NSIDE] = {};
+  hipEvent_t side_ev[NSIDE + 1] = {};
   hipEvent_t order_in = nullptr, order_out = nullptr;
   std::vector<hipEvent_t> events;
   hipEvent_t ev_start = nullptr, ev_setup = nullptr, ev_end = nullptr;
