@@ -260,6 +260,7 @@ def main():
         "metric": "GB/s of field corrected on 1 MI355X (plain vs batched); p50/p99 job latency",
         "value": round(value, 3),
         "unit": "GB/s",
+        "value_GiBps": round(n * b / (ms * 1e-3) / 2 ** 30, 3),  # the paper quotes GiB/s
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
