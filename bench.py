@@ -180,6 +180,9 @@ def main():
                     help="skip the batched and serving measurements")
     ap.add_argument("--serve-jobs", type=int, default=200, help="jobs in the serving trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 96-field batched workload (for profiling) and print its "
+                         "figures as one JSON line")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write elementwise kernel 3 times "
                          "(scale for the HBM traffic counters)")
@@ -203,6 +206,10 @@ def main():
         return
 
     from paper_2604_01397_amd import exactz, synth
+
+    if args.batched_only:
+        print(json.dumps({"batched": run_batched(torch, exactz, synth)}), flush=True)
+        return
 
     t0 = time.time()
     case = synth.config2(args.edge)
