@@ -171,7 +171,10 @@ typedef struct {
  * convergence flags (Algorithm 1 run independently per field).  results[k]
  * is what exz_correct would return for fields[k], bit for bit.  Returns the
  * first error status among the fields, else EXZ_OK (warnings are per
- * field). */
+ * field).  The fields' set-up runs on streams owned by the context (so the
+ * small kernels of different fields overlap) and the iterations on the
+ * context's own stream; all of it starts after the work already issued on
+ * `stream` and completes before anything issued on `stream` afterwards. */
 exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfields,
                              exz_result *results, void *stream);
 
