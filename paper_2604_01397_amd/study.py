@@ -76,7 +76,8 @@ def table1(torch, exactz, synth, edges=(128, 256, 512), rel=1e-4, n_steps=5):
             torch.cuda.synchronize()
             log("%s: corrected (%d iterations)" % (name, r["iterations"]))
             t0 = time.perf_counter()
-            m = vulnerability.metrics(f.view(-1), g.view(-1), xi, (edge, edge, edge))
+            m = vulnerability.metrics(f.view(-1), g.view(-1), xi, (edge, edge, edge),
+                                      log=lambda s, name=name: log("%s: %s" % (name, s)))
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             n = fh.size
