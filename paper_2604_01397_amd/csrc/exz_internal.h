@@ -100,7 +100,8 @@ struct FieldDev {
   void *cpv;            // K: current value of every critical point of f, in vertex order
   uint32_t *cp_idx;     // K, rank -> vertex
   uint32_t *sad_rank;   // saddle order -> rank in the CP order (K capacity)
-  uint32_t *sel_f;      // 2 per saddle: selections in f (join, split) or ~0
+  uint32_t *sel_f;      // 2 per critical point, in vertex order: selections in f (join,
+                        // split) or ~0
   uint32_t *lab;        // 2n: g's descent / ascent labels (original mode)
   uint32_t *lab_f;      // 2n: f's resolved path termini (original mode, certificate)
   uint8_t *tmark;       // n: the target set of the iteration (1 = decrease this vertex)

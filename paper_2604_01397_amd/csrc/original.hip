@@ -117,12 +117,20 @@ __device__ __forceinline__ uint32_t select_extremum(const FieldDev &fd, const T 
   return best;
 }
 
+// Selections of f, per critical point in vertex order (slot vo of cp_vtx):
+// neighbouring threads then read neighbouring vertices.  Critical points
+// that are not saddles select nothing.
 template <class T>
 __global__ void k_select_f(FieldDev fd, const uint8_t *comp) {
   const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= fd.st->nsaddle) return;
+  if (k >= (uint32_t)fd.K) return;
   const T *F = (const T *)fd.f;
-  const uint32_t s = fd.cp_idx[fd.sad_rank[k]];
+  const uint32_t s = fd.cp_vtx[k];
+  if (!(fd.low[s] & LOW_SADDLE)) {
+    fd.sel_f[2 * k] = NONE;
+    fd.sel_f[2 * k + 1] = NONE;
+    return;
+  }
   int x, y, z;
   coords(fd, s, x, y, z);
   const uint32_t vm = valid_slots(x, y, z, fd.nx, fd.ny, fd.nz);
@@ -137,17 +145,18 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   if (st->done) return;
   const uint32_t k = blockIdx.x * 256 + threadIdx.x;
   const uint32_t ns = st->nsaddle;
-  if (k >= ns) return;
   const T *G = (const T *)fd.g;
   const T *F = (const T *)fd.f;
-  const uint32_t rk = fd.sad_rank[k];
-  const uint32_t s = fd.cp_idx[rk];
-  // C2: saddle order
+  // C2: saddle order (thread k takes the k-th saddle in f's order)
   if (k + 1 < ns) {
+    const uint32_t s = fd.cp_idx[fd.sad_rank[k]];
     const uint32_t sn = fd.cp_idx[fd.sad_rank[k + 1]];
     if (sos_lt(G[sn], sn, G[s], s)) mark_target(fd.tmark, s);
   }
-  // C3: selected extrema along the integral paths of g
+  // C3: selected extrema along the integral paths of g (thread k takes the
+  // critical point in vertex-order slot k)
+  if (k >= (uint32_t)fd.K) return;
+  const uint32_t s = fd.cp_vtx[k];
   const uint32_t mf = fd.sel_f[2 * k], Mf = fd.sel_f[2 * k + 1];
   if (mf == NONE && Mf == NONE) return;
   int x, y, z;
