@@ -11,7 +11,8 @@
 // lab[0, n), ascent labels lab[n, 2n) (stored as n + vertex).
 //
 // Per iteration (original mode): the check pass also writes g's pointers,
-// the rounds resolve them, and one kernel per saddle applies
+// the rounds resolve them, and one kernel applies (C2 with a thread per
+// saddle in f's order, C3 with a thread per critical point in vertex order)
 //   C2  consecutive saddles of f keep their order in g (the lower one in f
 //       goes down when inverted), and
 //   C3  the selection in g equals the selection in f; otherwise the lower of
