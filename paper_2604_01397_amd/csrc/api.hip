@@ -281,7 +281,8 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
 void layout_c(const FieldDev &fd, bool original, bool certify, Layout &L, size_t off[6]) {
   const size_t n = (size_t)fd.n, K = (size_t)(fd.K ? fd.K : 1);
   off[0] = (original || certify) ? L.add(8 * n) : 0;  // lab_f
-  off[1] = (original || certify) ? L.add(8 * n) : 0;  // lab (g) / certificate labels
+  // lab (g) / certificate labels, then the convergence bitmask of 2n labels
+  off[1] = (original || certify) ? L.add(8 * n + 4 * jump_conv_words(2 * (uint64_t)n)) : 0;
   off[2] = original ? L.add(4 * K) : 0;               // sad_rank
   off[3] = original ? L.add(8 * K) : 0;               // sel_f
   off[4] = original ? L.add(4 * (K + 1)) : 0;         // saddle flags / prefix

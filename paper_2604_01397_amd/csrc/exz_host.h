@@ -51,6 +51,8 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
               size_t off[9]);
 void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]);
 hipError_t launch_iota(uint32_t *v, uint32_t n, hipStream_t s);
+// 32-bit words of the pointer-jumping convergence bitmask of count labels.
+size_t jump_conv_words(uint64_t count);
 void layout_c(const FieldDev &fd, bool original, bool certify, Layout &L, size_t off[6]);
 exz_status setup_paths(exz_ctx *ctx, FieldDev &fd, bool original, bool certify, Arena &C,
                        uint32_t **lab_g, hipStream_t s);

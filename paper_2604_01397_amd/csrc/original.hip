@@ -50,24 +50,46 @@ __global__ void k_ptr_f(FieldDev fd, uint32_t *lab) {
 }
 
 // One pointer-jumping round over count labels; flag[round] records whether
-// anything moved.  A round after an unchanged one returns at once.
-__global__ void k_jump(uint32_t *lab, uint32_t count, State *st, int round, int honour_done) {
+// anything moved.  A round after an unchanged one returns at once.  A label
+// whose target points at itself has reached its chain's end and never
+// changes again: bit v of conv records that, so later rounds read one
+// 32-bit word per 32 such labels instead of the labels.  Each wave takes 64
+// consecutive labels, i.e. two whole words of conv, and is their only
+// writer.
+__global__ void k_jump(uint32_t *lab, uint32_t count, uint32_t *conv, State *st, int round,
+                       int honour_done) {
   if (honour_done && st->done) return;
   if (round > 0 && st->jump[round - 1] == 0) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  const unsigned long long wave = (blockIdx.x * 256ull + threadIdx.x) >> 6;
+  const unsigned long long waves = gridDim.x * 4ull;
   bool moved = false;
-  for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < count; v += gridDim.x * 256) {
-    const uint32_t p = lab[v];
-    const uint32_t q = lab[p];
-    if (q != p) {
-      lab[v] = q;
-      moved = true;
+  for (unsigned long long base = wave * 64; base < count; base += waves * 64) {
+    const uint32_t v = (uint32_t)base + lane;
+    const uint32_t w = (uint32_t)(base >> 5) + (lane >> 5);
+    const uint32_t old = conv[w];
+    bool fin = (unsigned long long)v >= count || ((old >> (lane & 31u)) & 1u);
+    if (!fin) {
+      const uint32_t p = lab[v];
+      const uint32_t q = lab[p];
+      if (q != p) {
+        lab[v] = q;
+        moved = true;
+      } else {
+        fin = true;
+      }
     }
+    const unsigned long long b = __ballot(fin);
+    const uint32_t nw = lane < 32 ? (uint32_t)b : (uint32_t)(b >> 32);
+    if ((lane & 31u) == 0 && nw != old) conv[w] = nw;
   }
   if (__any(moved) && __lane_id() == 0) st->jump[round] = 1u;
 }
 
-__global__ void k_jump_reset(State *st) {
-  if (threadIdx.x < MAX_JUMP_ROUNDS) st->jump[threadIdx.x] = 0;
+__global__ void k_jump_reset(State *st, uint32_t *conv, uint32_t words) {
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t < MAX_JUMP_ROUNDS) st->jump[t] = 0;
+  for (uint32_t k = t; k < words; k += gridDim.x * 256) conv[k] = 0;
 }
 
 int jump_rounds(uint32_t count) {
@@ -76,14 +98,25 @@ int jump_rounds(uint32_t count) {
   return r;
 }
 
-static hipError_t jump_all(uint32_t *lab, uint32_t count, State *st, int honour_done,
+// Words of the convergence bitmask of count labels: two per 64 labels.
+size_t jump_conv_words(uint64_t count) { return (size_t)((count + 63) / 64) * 2; }
+
+// Resolves count labels.  The convergence bitmask lives right after the
+// 2n labels of fd.lab (the caller's layout reserves it there); the labels
+// resolved here may be fd.lab's own or another array of 2n labels.
+static hipError_t jump_all(const FieldDev &fd, uint32_t *lab, uint32_t count, int honour_done,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_jump_reset, dim3(1), dim3(64), 0, s, st);
+  uint32_t *conv = fd.lab + 2 * (size_t)fd.n;
+  const uint32_t words = (uint32_t)jump_conv_words(count);
+  const uint32_t gw = (words + 255) / 256;
+  hipLaunchKernelGGL(k_jump_reset, dim3(gw < 1024 ? (gw ? gw : 1) : 1024), dim3(256), 0, s, fd.st,
+                     conv, words);
   const uint32_t g = (count + 255) / 256;
   const int grid = (int)(g < 4096 ? (g ? g : 1) : 4096);
   const int rounds = jump_rounds(count);
   for (int r = 0; r < rounds; ++r)
-    hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, s, lab, count, st, r, honour_done);
+    hipLaunchKernelGGL(k_jump, dim3(grid), dim3(256), 0, s, lab, count, conv, fd.st, r,
+                       honour_done);
   return hipGetLastError();
 }
 
@@ -253,7 +286,7 @@ hipError_t launch_original_setup(const FieldDev &fd, const uint8_t *comp, uint32
   hipLaunchKernelGGL(k_saddle_scatter, dim3(gk), dim3(256), 0, s, fd, tmp);
   const int gn = (fd.n + 255) / 256;
   hipLaunchKernelGGL(k_ptr_f, dim3(gn), dim3(256), 0, s, fd, fd.lab_f);
-  e = jump_all(fd.lab_f, 2u * (uint32_t)fd.n, fd.st, 0, s);
+  e = jump_all(fd, fd.lab_f, 2u * (uint32_t)fd.n, 0, s);
   if (e != hipSuccess) return e;
   if (fd.dtype == 0)
     hipLaunchKernelGGL(k_select_f<float>, dim3(gk), dim3(256), 0, s, fd, comp);
@@ -263,7 +296,7 @@ hipError_t launch_original_setup(const FieldDev &fd, const uint8_t *comp, uint32
 }
 
 hipError_t launch_original_events(const FieldDev &fd, const uint8_t *comp, hipStream_t s) {
-  hipError_t e = jump_all(fd.lab, 2u * (uint32_t)fd.n, fd.st, 1, s);
+  hipError_t e = jump_all(fd, fd.lab, 2u * (uint32_t)fd.n, 1, s);
   if (e != hipSuccess) return e;
   const int gk = (fd.K + 255) / 256 ? (fd.K + 255) / 256 : 1;
   if (fd.dtype == 0)
@@ -278,14 +311,14 @@ hipError_t launch_certify(const FieldDev &fd, const uint8_t *comp, uint32_t *lab
   const int gn = (fd.n + 255) / 256;
   if (fd.mode != EXZ_EVENT_ORIGINAL) {  // f's resolved labels are built on demand
     hipLaunchKernelGGL(k_ptr_f, dim3(gn), dim3(256), 0, s, fd, fd.lab_f);
-    hipError_t e = jump_all(fd.lab_f, 2u * (uint32_t)fd.n, fd.st, 0, s);
+    hipError_t e = jump_all(fd, fd.lab_f, 2u * (uint32_t)fd.n, 0, s);
     if (e != hipSuccess) return e;
   }
   if (fd.dtype == 0)
     hipLaunchKernelGGL(k_ptr_g<float>, dim3(gn), dim3(256), 0, s, fd, lab_g);
   else
     hipLaunchKernelGGL(k_ptr_g<double>, dim3(gn), dim3(256), 0, s, fd, lab_g);
-  hipError_t e = jump_all(lab_g, 2u * (uint32_t)fd.n, fd.st, 0, s);
+  hipError_t e = jump_all(fd, lab_g, 2u * (uint32_t)fd.n, 0, s);
   if (e != hipSuccess) return e;
   if (fd.dtype == 0)
     hipLaunchKernelGGL(k_cert_compare<float>, dim3(gn), dim3(256), 0, s, fd, comp, lab_g);
