@@ -176,6 +176,51 @@ def extremum_graph(cx: Complex, h, info=None):
     return cps, edges
 
 
+def saddle_sequence(cx: Complex, f, h):
+    """Saddles of f (by the brute-force link analysis of f), listed in
+    ascending SoS order of h.  The saddle ordering constraint (Sec. 4.2, C2)
+    holds on h exactly when this equals the list in f's order."""
+    f = np.asarray(f).ravel()
+    h = np.asarray(h).ravel()
+    info = classify(cx, f)
+    sad = [v for v in range(cx.n) if info[v]["type"] == SADDLE]
+    return sorted(sad, key=lambda v: (h[v], v))
+
+
+def event_selections(cx: Complex, f, h):
+    """Per saddle of f, the extremum EGP pairs it with in h (Sec. 4.2, C3).
+
+    For a join saddle s of f (lower link of s in f has two or more pieces):
+    the highest minimum in h among the minima that steepest-descent paths of
+    h reach from the lower neighbours of s in h.  For a split saddle of f:
+    the lowest maximum among those steepest-ascent paths of h reach from its
+    upper neighbours in h.  Paths, links and pointers are the checker's own
+    (simplicial complex, closed-neighbourhood SoS pointers).  Returns a dict
+    {(s, "join"|"split"): extremum}.
+    """
+    f = np.asarray(f).ravel()
+    h = np.asarray(h).ravel()
+    fi = classify(cx, f)
+    hi = classify(cx, h)
+
+    def term(v, key):
+        while hi[v][key] != v:
+            v = hi[v][key]
+        return v
+
+    out = {}
+    for s in range(cx.n):
+        if fi[s]["type"] != SADDLE:
+            continue
+        if fi[s]["lc"] >= 2 and hi[s]["lower"]:
+            reach = {term(k, "desc") for k in hi[s]["lower"]}
+            out[(s, "join")] = max(reach, key=lambda m: (h[m], m))
+        if fi[s]["uc"] >= 2 and hi[s]["upper"]:
+            reach = {term(k, "asc") for k in hi[s]["upper"]}
+            out[(s, "split")] = min(reach, key=lambda m: (h[m], m))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # merge trees and contour tree (union-find sweeps)
 

@@ -366,7 +366,12 @@ int64_t check(const Reference &R, const T *f, const T *g, int mode,
     // Saddle ordering constraints (C2): consecutive saddles of f.
     for (size_t k = 0; k + 1 < R.saddles.size(); ++k)
       if (lt(g, R.saddles[k + 1], R.saddles[k])) mark[R.saddles[k]] = 1;
-    // Event constraints (C3) by integral-path tracing in g.
+    // Event constraints (C3) by integral-path tracing in g.  When the
+    // extremum a saddle selects in g differs from its selection in f, the
+    // edit goes where Sec. 4.2 puts it: a join saddle lowers the minimum g
+    // selects until it sits below f's choice; a split saddle, by the same
+    // argument with decreasing edits only, lowers f's choice of maximum until
+    // it sits below the one g selects.
     for (size_t k = 0; k < R.saddles.size(); ++k) {
       const int64_t s = R.saddles[k];
       neighbours(m, s, nb);
@@ -380,7 +385,7 @@ int64_t check(const Reference &R, const T *f, const T *g, int mode,
             const int64_t t = terminus(gdesc, p.second);
             if (sel < 0 || lt(g, sel, t)) sel = t;
           }
-        if (sel >= 0 && sel != R.mf[k]) mark[lt(f, sel, R.mf[k]) ? sel : R.mf[k]] = 1;
+        if (sel >= 0 && sel != R.mf[k]) mark[sel] = 1;
       }
       if (R.uc[s] >= 2) {
         int64_t sel = -1;
@@ -389,7 +394,7 @@ int64_t check(const Reference &R, const T *f, const T *g, int mode,
             const int64_t t = terminus(gasc, p.second);
             if (sel < 0 || lt(g, t, sel)) sel = t;
           }
-        if (sel >= 0 && sel != R.Mf[k]) mark[lt(f, sel, R.Mf[k]) ? sel : R.Mf[k]] = 1;
+        if (sel >= 0 && sel != R.Mf[k]) mark[R.Mf[k]] = 1;
       }
     }
   }

@@ -371,6 +371,7 @@ exz_status exz_ctx_destroy(exz_ctx *ctx) {
   if (ctx->step_host) (void)hipHostFree(ctx->step_host);
   if (ctx->step_dev) (void)hipFree(ctx->step_dev);
   if (ctx->step_copied) (void)hipEventDestroy(ctx->step_copied);
+  if (ctx->step_done) (void)hipEventDestroy(ctx->step_done);
   if (ctx->order_in) (void)hipEventDestroy(ctx->order_in);
   if (ctx->order_out) (void)hipEventDestroy(ctx->order_out);
   if (ctx->work) (void)hipStreamDestroy(ctx->work);
@@ -425,6 +426,17 @@ exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value) {
       return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d", ty, tz);
     ctx->tile_y = ty;
     ctx->tile_z = tz;
+  } else if (k == "btile3" || k == "btile2") {  // batched / job boxes, 0 = default
+    const int ty = (int)(value / 100), tz = (int)(value % 100);
+    if (value != 0 && (!box_supported(ty, tz) || (k == "btile2" && tz != 1)))
+      return fail(ctx, EXZ_E_INVALID, "no compiled box %d x %d for %s", ty, tz, key);
+    (k == "btile3" ? ctx->btile3 : ctx->btile2) = (int)value;
+  } else if (k == "bgrid_box" || k == "bgrid_apply") {  // batched grid caps, 0 = default
+    if (value < 0 || value > (1 << 20)) return fail(ctx, EXZ_E_INVALID, "%s must be 0..2^20", key);
+    (k == "bgrid_box" ? ctx->bgrid_box : ctx->bgrid_apply) = (int)value;
+  } else if (k == "bitem") {  // batched apply item: quads per thread, 0 = default (16)
+    if (value < 0 || value > 256) return fail(ctx, EXZ_E_INVALID, "bitem must be 0..256");
+    ctx->bitem = (int)value;
   } else {
     return fail(ctx, EXZ_E_INVALID, "unknown option '%s'", key);
   }

@@ -77,14 +77,16 @@ __global__ void __launch_bounds__(64 * TY)
   }
 }
 
-// Vertices of one batched apply item: sixteen quads per thread, so the
-// item's set-up (finding its field, reading its descriptor) is amortised.
+// Vertices of one batched apply item: item_quads quads (by default sixteen
+// per thread), so the item's set-up (finding its field, reading its
+// descriptor) is amortised.
 constexpr uint32_t APPLY_ITEM_QUADS = 16 * APPLY_BLOCK;
 
 // ApplyBoundedEdits: field k owns items [base[k], base[k+1]), one per
-// 4 * APPLY_ITEM_QUADS vertices.
+// 4 * item_quads vertices.
 __global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *__restrict__ fields,
-                                                             const uint32_t *__restrict__ lists) {
+                                                             const uint32_t *__restrict__ lists,
+                                                             uint32_t item_quads) {
   const uint32_t nf = lists[0], total = lists[1];
   const uint32_t *field = lists + 2, *base = lists + 2 + nf;
   // counts are added to a field's shards when the block moves on to the
@@ -100,8 +102,8 @@ __global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *__r
     }
     const FieldDev &fd = fields[__builtin_amdgcn_readfirstlane(field[k])];
     if (!fd.st->done) {
-      const uint32_t q0 = (it - base[k]) * APPLY_ITEM_QUADS;
-      const uint32_t nq = min(((uint32_t)fd.n + 3) / 4, q0 + APPLY_ITEM_QUADS);
+      const uint32_t q0 = (it - base[k]) * item_quads;
+      const uint32_t nq = min(((uint32_t)fd.n + 3) / 4, q0 + item_quads);
       if (fd.dtype == 0)
         apply_quads<float>(fd, q0 + threadIdx.x, APPLY_BLOCK, nq, ec);
       else
@@ -163,11 +165,53 @@ struct Member {
 
 namespace exz {
 
-// Launch geometry shared by all members of a batch.
+// Launch geometry shared by all members of a batch (context options
+// "btile3", "btile2", "bgrid_box", "bgrid_apply", "bitem"; 0 = default).
 struct BatchShape {
   int ty3 = 4, tz3 = 8;  // boxes for 3D fields
   int ty2 = 16, tz2 = 1; // boxes for 1D/2D fields
+  int grid_box = 0;      // persistent check grid cap (0: 8 work-groups per CU)
+  int grid_apply = 0;    // persistent apply grid cap (0: 16 work-groups per CU)
+  uint32_t item_quads = APPLY_ITEM_QUADS;  // quads per apply item
 };
+
+BatchShape batch_shape(const exz_ctx *ctx) {
+  BatchShape b;
+  if (ctx->btile3) {
+    b.ty3 = ctx->btile3 / 100;
+    b.tz3 = ctx->btile3 % 100;
+  } else if (ctx->tile_y && ctx->tile_z) {  // an explicit "tile" applies to 3D members
+    b.ty3 = ctx->tile_y;
+    b.tz3 = ctx->tile_z;
+  }
+  if (ctx->btile2) {
+    b.ty2 = ctx->btile2 / 100;
+    b.tz2 = ctx->btile2 % 100;
+  }
+  b.grid_box = ctx->bgrid_box;
+  b.grid_apply = ctx->bgrid_apply;
+  if (ctx->bitem) b.item_quads = (uint32_t)ctx->bitem * APPLY_BLOCK;
+  return b;
+}
+
+// Box geometry of a member for the batch's shape.
+void batch_geometry(const BatchShape &b, FieldDev &fd) {
+  const bool three = fd.nz > 1;
+  fd.tile_y = three ? b.ty3 : b.ty2;
+  fd.tile_z = three ? b.tz3 : b.tz2;
+  fd.ty_shift = __builtin_ctz((unsigned)fd.tile_y);
+  fd.tz_shift = __builtin_ctz((unsigned)fd.tile_z);
+  fd.tiles_y = (fd.ny + fd.tile_y - 1) / fd.tile_y;
+  fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
+  fd.ntiles = fd.tiles_x * fd.tiles_y * fd.tiles_z;
+}
+
+// Persistent grids: enough work-groups to fill the chip, never more than
+// there are items.
+int batch_grid(uint64_t items, int cap, int per_cu) {
+  const uint64_t c = cap > 0 ? (uint64_t)cap : (uint64_t)256 * per_cu;
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>(items, c));
+}
 
 // Host-built item lists for one phase, in pinned memory.
 struct Lists {
@@ -217,6 +261,7 @@ static void box_launch_check(int ty, int tz, const FieldDev *fields, const uint3
 static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dlists, size_t lw,
                              const BatchShape &shape, int iters, int grid_box,
                              int grid_fin, int grid_apply, hipStream_t s) {
+  const uint32_t item_quads = shape.item_quads;
   auto list = [&](int q) { return dlists + q * lw; };
   uint32_t *lf = list(L_FIN), *la = list(L_APPLY);
   for (int it = 0; it < iters; ++it) {
@@ -224,17 +269,18 @@ static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dli
     box_launch_check<double>(shape.ty3, shape.tz3, fields, list(L_BOX3D), ctx->d_conn, grid_box, s);
     box_launch_check<float>(shape.ty2, shape.tz2, fields, list(L_BOX2F), ctx->d_conn, grid_box, s);
     box_launch_check<double>(shape.ty2, shape.tz2, fields, list(L_BOX2D), ctx->d_conn, grid_box, s);
-    hipLaunchKernelGGL(k_apply_batch, dim3(grid_apply), dim3(APPLY_BLOCK), 0, s, fields, la);
+    hipLaunchKernelGGL(k_apply_batch, dim3(grid_apply), dim3(APPLY_BLOCK), 0, s, fields, la,
+                       item_quads);
     hipLaunchKernelGGL(k_finalize_batch, dim3(grid_fin), dim3(64), 0, s, fields, lf);
   }
 }
 
-static uint32_t apply_items(const FieldDev &fd);
+static uint32_t apply_items(const FieldDev &fd, uint32_t item_quads);
 
 // Host item lists of one batched iteration over the fields fds[k] with
 // active[k], written into the pinned buffer hl (NLISTS lists of lw words).
 static void build_lists(const std::vector<const FieldDev *> &fds, const std::vector<bool> &active,
-                        uint32_t *hl, size_t lw) {
+                        uint32_t item_quads, uint32_t *hl, size_t lw) {
   std::vector<int> f[NLISTS];
   std::vector<uint32_t> n[NLISTS];
   for (size_t k = 0; k < fds.size(); ++k) {
@@ -248,7 +294,7 @@ static void build_lists(const std::vector<const FieldDev *> &fds, const std::vec
     f[L_FIN].push_back(idx);
     n[L_FIN].push_back(1);
     f[L_APPLY].push_back(idx);
-    n[L_APPLY].push_back(apply_items(fd));
+    n[L_APPLY].push_back(apply_items(fd, item_quads));
   }
   for (int q = 0; q < NLISTS; ++q) {
     Lists L;
@@ -257,10 +303,10 @@ static void build_lists(const std::vector<const FieldDev *> &fds, const std::vec
   }
 }
 
-// Items of the apply pass of one field: 4 * APPLY_ITEM_QUADS vertices each.
-static uint32_t apply_items(const FieldDev &fd) {
+// Items of the apply pass of one field: 4 * item_quads vertices each.
+static uint32_t apply_items(const FieldDev &fd, uint32_t item_quads) {
   const uint32_t nq = ((uint32_t)fd.n + 3) / 4;
-  return (nq + APPLY_ITEM_QUADS - 1) / APPLY_ITEM_QUADS;
+  return (nq + item_quads - 1) / item_quads;
 }
 
 exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *dev_fields,
@@ -289,10 +335,10 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   uint64_t max_boxes = 0, max_apply = 0;
   for (auto &m : members) {
     max_boxes += (uint64_t)m.fd.ntiles;
-    max_apply += apply_items(m.fd);
+    max_apply += apply_items(m.fd, shape.item_quads);
   }
-  const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_boxes, 256 * 8));
-  const int grid_apply = (int)std::max<uint64_t>(1, std::min<uint64_t>(max_apply, 256 * 16));
+  const int grid_box = batch_grid(max_boxes, shape.grid_box, 8);
+  const int grid_apply = batch_grid(max_apply, shape.grid_apply, 16);
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   hipGraphExec_t exec = nullptr;
   int exec_chunk = 0;
@@ -308,7 +354,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
       any |= act[k];
     }
     if (!any) break;
-    build_lists(fds, act, hl, lw);
+    build_lists(fds, act, shape.item_quads, hl, lw);
     HIP_OR_FAIL_B(hipMemcpyAsync(dlists, hl, NLISTS * lw * sizeof(uint32_t),
                                  hipMemcpyHostToDevice, s));
     if (ctx->graph) {
@@ -336,13 +382,23 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
     HIP_OR_FAIL_B(hipMemcpyAsync(hstates, members[0].fd.st, nf * sizeof(State),
                                  hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL_B(hipStreamSynchronize(s));
-    for (size_t k = 0; k < nf; ++k)
-      if (members[k].active && hstates[k].done != RUNNING) members[k].active = false;
+    for (size_t k = 0; k < nf; ++k) {
+      if (!members[k].active) continue;
+      if (hstates[k].done != RUNNING) {
+        members[k].active = false;
+        continue;
+      }
+      // every changing iteration lowers a value and a vertex moves at most
+      // N + 1 times; two more passes may change nothing (frontier, then dense)
+      const int64_t cap = (int64_t)(members[k].fd.N + 1) * members[k].fd.n + 4;
+      if (hstates[k].passes > cap) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        return fail_b(ctx, EXZ_E_HIP, "batched loop did not terminate");
+      }
+    }
     if (ctx->poll == 0) chunk = std::min(chunk * 2, 32);
   }
   if (exec) (void)hipGraphExecDestroy(exec);
-  for (auto &m : members)
-    if (m.active) return fail_b(ctx, EXZ_E_HIP, "batched loop did not terminate");
   return EXZ_OK;
 }
 
@@ -418,11 +474,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
   }
   std::vector<Member> mem;
   std::vector<int> singles;  // fields run through the single-field driver
-  BatchShape shape;
-  if (ctx->tile_y) {  // an explicit box shape applies to the 3D members
-    shape.ty3 = ctx->tile_y;
-    shape.tz3 = ctx->tile_z;
-  }
+  const BatchShape shape = batch_shape(ctx);
   for (int k = 0; k < nfields; ++k) {
     const exz_field &fl = fields[k];
     Member m;
@@ -442,14 +494,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       continue;
     }
     // box shape of the batch for this field's dimensionality
-    const bool three = m.fd.nz > 1;
-    m.fd.tile_y = three ? shape.ty3 : shape.ty2;
-    m.fd.tile_z = three ? shape.tz3 : shape.tz2;
-    m.fd.ty_shift = __builtin_ctz((unsigned)m.fd.tile_y);
-    m.fd.tz_shift = __builtin_ctz((unsigned)m.fd.tile_z);
-    m.fd.tiles_y = (m.fd.ny + m.fd.tile_y - 1) / m.fd.tile_y;
-    m.fd.tiles_z = (m.fd.nz + m.fd.tile_z - 1) / m.fd.tile_z;
-    m.fd.ntiles = m.fd.tiles_x * m.fd.tiles_y * m.fd.tiles_z;
+    batch_geometry(shape, m.fd);
     m.fd.f = fl.f;
     m.fd.g_hat = fl.g_hat;
     m.fd.g = fl.g_out;
@@ -578,6 +623,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     {
       std::vector<Member> all = mem;  // slot k == device index k
       const exz_status ls = run_batch_loop(ctx, all, dev_fields, shape, 1 << 30, s);
+      // (the loop stops each member at its own pass cap)
       if (ls != EXZ_OK) return ls;
     }
     // certificates, then results
@@ -660,19 +706,20 @@ exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, ex
   exz_status st = prepare_field(ctx, &field->params, job->fd);
   if (st == EXZ_OK) {
     FieldDev &fd = job->fd;
-    const bool three = fd.nz > 1;  // same boxes as the batched launches
-    const BatchShape shape;
-    fd.tile_y = three ? shape.ty3 : shape.ty2;
-    fd.tile_z = three ? shape.tz3 : shape.tz2;
-    fd.ty_shift = __builtin_ctz((unsigned)fd.tile_y);
-    fd.tz_shift = __builtin_ctz((unsigned)fd.tile_z);
-    fd.tiles_y = (fd.ny + fd.tile_y - 1) / fd.tile_y;
-    fd.tiles_z = (fd.nz + fd.tile_z - 1) / fd.tile_z;
-    fd.ntiles = fd.tiles_x * fd.tiles_y * fd.tiles_z;
+    batch_geometry(batch_shape(ctx), fd);  // the boxes of the batched launches
     st = setup_field(ctx, fd, field->f, field->g_hat, field->g_out, field->cnt_io,
                      field->params.max_iters, job->A, job->B, (hipStream_t)stream);
   }
+  // The set-up's last kernels (critical-point order) are still queued on
+  // `stream`: the first step that takes the job waits for this event.
+  if (st == EXZ_OK && hipEventCreateWithFlags(&job->ready, hipEventDisableTiming) != hipSuccess) {
+    job->ready = nullptr;
+    st = fail_b(ctx, EXZ_E_HIP, "hipEventCreateWithFlags failed");
+  }
+  if (st == EXZ_OK && hipEventRecord(job->ready, (hipStream_t)stream) != hipSuccess)
+    st = fail_b(ctx, EXZ_E_HIP, "hipEventRecord failed");
   if (st != EXZ_OK) {
+    if (job->ready) (void)hipEventDestroy(job->ready);
     job->A.release();
     job->B.release();
     delete job;
@@ -708,28 +755,54 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   }
   FieldDev *hf = (FieldDev *)ctx->step_host;
   uint32_t *hl = (uint32_t *)(hf + nf);
+  // launch geometry: the jobs' own boxes (fixed when they were created), the
+  // context's grid caps and apply item size
+  BatchShape shape = batch_shape(ctx);
+  bool have3 = false, have2 = false;
+  for (size_t k = 0; k < nf; ++k) {
+    if (!jobs[k]) return fail_b(ctx, EXZ_E_INVALID, "null job");
+    const FieldDev &fd = jobs[k]->fd;
+    int &ty = fd.nz > 1 ? shape.ty3 : shape.ty2, &tz = fd.nz > 1 ? shape.tz3 : shape.tz2;
+    bool &have = fd.nz > 1 ? have3 : have2;
+    if (!have) {
+      ty = fd.tile_y;
+      tz = fd.tile_z;
+      have = true;
+    } else if (ty != fd.tile_y || tz != fd.tile_z) {
+      return fail_b(ctx, EXZ_E_INVALID, "jobs of one step must share their box shape");
+    }
+  }
   uint64_t boxes = 0, words = 0;
   std::vector<const FieldDev *> fds(nf);
   std::vector<bool> act(nf, true);
+  // Stream order: this step starts after the previous step (which read the
+  // device copy of the descriptors that is rewritten below, maybe on another
+  // stream) and after the set-up of every job it takes for the first time.
+  if (ctx->step_done) HIP_OR_FAIL_B(hipStreamWaitEvent(s, ctx->step_done, 0));
+  else HIP_OR_FAIL_B(hipEventCreateWithFlags(&ctx->step_done, hipEventDisableTiming));
   for (size_t k = 0; k < nf; ++k) {
-    if (!jobs[k]) return fail_b(ctx, EXZ_E_INVALID, "null job");
-    hf[k] = jobs[k]->fd;
+    exz_job *job = jobs[k];
+    if (!job->joined) {
+      HIP_OR_FAIL_B(hipStreamWaitEvent(s, job->ready, 0));
+      job->joined = true;
+    }
+    hf[k] = job->fd;
     const FieldDev &fd = hf[k];
     fds[k] = &hf[k];
-    words += apply_items(fd);
+    words += apply_items(fd, shape.item_quads);
     boxes += (uint64_t)fd.ntiles;
-    jobs[k]->last = s;
+    job->last = s;
   }
-  build_lists(fds, act, hl, lw);
+  build_lists(fds, act, shape.item_quads, hl, lw);
   FieldDev *df = (FieldDev *)ctx->step_dev;
   uint32_t *dl = (uint32_t *)(df + nf);
   HIP_OR_FAIL_B(hipMemcpyAsync(df, hf, bytes, hipMemcpyHostToDevice, s));
   HIP_OR_FAIL_B(hipEventRecord(ctx->step_copied, s));
-  BatchShape shape;  // jobs use the default boxes (3D 4 x 8, 2D 16 x 1)
-  const int grid_box = (int)std::max<uint64_t>(1, std::min<uint64_t>(boxes, 256 * 8));
-  const int grid_apply = (int)std::max<uint64_t>(1, std::min<uint64_t>(words, 256 * 16));
+  const int grid_box = batch_grid(boxes, shape.grid_box, 8);
+  const int grid_apply = batch_grid(words, shape.grid_apply, 16);
   issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, (int)nf, grid_apply, s);
   HIP_OR_FAIL_B(hipGetLastError());
+  HIP_OR_FAIL_B(hipEventRecord(ctx->step_done, s));
   return EXZ_OK;
 }
 
@@ -757,6 +830,10 @@ exz_status exz_job_release(exz_job *job) {
   if (!job) return EXZ_OK;
   (void)hipSetDevice(job->ctx->device);
   if (job->last) (void)hipStreamSynchronize(job->last);
+  if (job->ready) {
+    (void)hipEventSynchronize(job->ready);
+    (void)hipEventDestroy(job->ready);
+  }
   job->A.release();
   job->B.release();
   delete job;

@@ -80,7 +80,12 @@ struct exz_ctx {
   void *step_host = nullptr;  // exz_step staging: pinned FieldDev array + item lists
   void *step_dev = nullptr;
   size_t step_cap = 0;
-  hipEvent_t step_copied = nullptr;
+  hipEvent_t step_copied = nullptr;  // the host staging of the last step was copied
+  hipEvent_t step_done = nullptr;    // the last step's launches (they read step_dev)
+  // batched / job launch geometry (0 = default): boxes for 3D and 2D members
+  // (tile_y * 100 + tile_z), grid caps of the check and apply passes, and
+  // apply item size in quads per thread
+  int btile3 = 0, btile2 = 0, bgrid_box = 0, bgrid_apply = 0, bitem = 0;
   hipStream_t work = nullptr;       // internal stream for captured work (default priority)
   // streams (default priority) over which the batched set-up of independent
   // fields is spread, and the events that fork them from / join them to the
@@ -104,5 +109,6 @@ struct exz_job {
   hipStream_t last = nullptr;   // stream of the last work issued for it
   exz_result result;
   bool finished = false;
-  hipEvent_t ev_setup = nullptr;
+  hipEvent_t ready = nullptr;  // set-up done (recorded on the creation stream)
+  bool joined = false;         // a step has waited for `ready`
 };

@@ -601,6 +601,9 @@ __device__ __forceinline__ void flush_counts(State *st, EditCount ec, uint32_t s
     for (int k = 0; k < TY; ++k) v += part[tid][k];
     if (v) atomicAdd(&st->shard[tid][shard & 63u], v);
   }
+  // a work-group may flush again (the batched apply does, once per field it
+  // moves on from): part must not be rewritten before it has been summed
+  __syncthreads();
 }
 
 constexpr uint32_t NOFLAG_PER_BOX = 4;

@@ -15,8 +15,10 @@
 // saddle in f's order, C3 with a thread per critical point in vertex order)
 //   C2  consecutive saddles of f keep their order in g (the lower one in f
 //       goes down when inverted), and
-//   C3  the selection in g equals the selection in f; otherwise the lower of
-//       the two selected extrema (in f) goes down.
+//   C3  the selection in g equals the selection in f; otherwise a join
+//       saddle lowers the minimum g selects (below f's choice) and a split
+//       saddle lowers f's choice of maximum (below g's), the edits Sec. 4.2
+//       prescribes with decreasing edits only.
 // The certificate compares the path termini of f and g' for every vertex and
 // all critical types: the extremum-graph identity of Sec. 4.1, C1.
 #include "exz_host.h"
@@ -180,7 +182,6 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   const uint32_t k = blockIdx.x * 256 + threadIdx.x;
   const uint32_t ns = st->nsaddle;
   const T *G = (const T *)fd.g;
-  const T *F = (const T *)fd.f;
   // C2: saddle order (thread k takes the k-th saddle in f's order)
   if (k + 1 < ns) {
     const uint32_t s = fd.cp_idx[fd.sad_rank[k]];
@@ -205,12 +206,12 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   }
   if (mf != NONE && glower) {
     const uint32_t mg = select_extremum(fd, G, fd.lab, s, glower, true);
-    if (mg != mf) mark_target(fd.tmark, sos_lt(F[mg], mg, F[mf], mf) ? mg : mf);
+    if (mg != mf) mark_target(fd.tmark, mg);
   }
   const uint32_t gupper = vm & ~glower;
   if (Mf != NONE && gupper) {
     const uint32_t Mg = select_extremum(fd, G, fd.lab, s, gupper, false);
-    if (Mg != Mf) mark_target(fd.tmark, sos_lt(F[Mg], Mg, F[Mf], Mf) ? Mg : Mf);
+    if (Mg != Mf) mark_target(fd.tmark, Mf);
   }
 }
 

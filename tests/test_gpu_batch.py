@@ -125,3 +125,53 @@ def test_batch_graph_and_poll_invariance(ctx):
         torch.cuda.synchronize()
         for a, b in zip(ref, out):
             assert torch.equal(a[0], b[0]) and a[2]["iterations"] == b[2]["iterations"]
+
+
+def test_batch_apply_blocks_cross_fields(ctx):
+    """With a tiny apply grid and one quad per thread per item, every apply
+    work-group walks items of several fields and flushes its edit counts
+    once per field: counters and results must still equal the plain runs
+    and the oracle."""
+    cases = _mixed_cases()
+    items = [{"f": _dev(c.f), "g_hat": _dev(c.g_hat), "xi": c.xi} for c in cases]
+    ref = ctx.correct_batch(items)
+    for grid, item in ((2, 1), (3, 2), (1, 1)):
+        ctx.set_option("bgrid_apply", grid)
+        ctx.set_option("bitem", item)
+        ctx.set_option("bgrid_box", 5)
+        try:
+            out = ctx.correct_batch(items)
+        finally:
+            ctx.set_option("bgrid_apply", 0)
+            ctx.set_option("bitem", 0)
+            ctx.set_option("bgrid_box", 0)
+        torch.cuda.synchronize()
+        print("apply grid", grid, "item", item, flush=True)
+        for c, a, b in zip(cases, ref, out):
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), c.name
+            for k in ("iterations", "edited_vertices", "edit_ops", "lossless_vertices",
+                      "floor_vertices", "residual_violations", "status"):
+                assert a[2][k] == b[2][k], (c.name, k)
+    for c, (g_out, cnt, r) in zip(cases, ref):
+        go, co, st, _ = oracle.correct(c.f, c.g_hat, c.xi)
+        assert np.array_equal(_bits(g_out.cpu().numpy()), _bits(go)), c.name
+        assert r["edit_ops"] == st["edit_ops"] and r["lossless_vertices"] == st["lossless_vertices"]
+
+
+def test_batch_box_shapes_invariance(ctx):
+    """Batched box shapes and grids chosen by the autotuner never change a
+    result."""
+    cases = _mixed_cases()
+    items = [{"f": _dev(c.f), "g_hat": _dev(c.g_hat), "xi": c.xi} for c in cases]
+    ref = ctx.correct_batch(items)
+    for b3, b2 in ((202, 401), (804, 801), (404, 101), (1602, 1601)):
+        ctx.set_option("btile3", b3)
+        ctx.set_option("btile2", b2)
+        try:
+            out = ctx.correct_batch(items)
+        finally:
+            ctx.set_option("btile3", 0)
+            ctx.set_option("btile2", 0)
+        torch.cuda.synchronize()
+        for c, a, b in zip(cases, ref, out):
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), (c.name, b3, b2)

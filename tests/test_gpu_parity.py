@@ -266,6 +266,25 @@ def test_original_mode_split_pair_case(ctx, golden):
     _compare_mode(ctx, f, g, float(gd["xi"][0]), "split-pair", 1, n_steps=int(gd["n_steps"][0]))
 
 
+@pytest.mark.parametrize("name", ["original_mode_join_c2_2d.txt", "original_mode_split_c2_2d.txt",
+                                  "original_mode_join_glink_2d.txt",
+                                  "original_mode_split_tie_2d.txt"])
+def test_original_mode_worked_examples(ctx, golden, name):
+    """The hand-built original-mode fixtures (C2 and both sides of C3 named
+    in the first iteration) against the fixture's own values and the oracle."""
+    gd = golden(name)
+    shape = tuple(reversed([int(v) for v in gd["dims"]]))
+    f = np.array([float(v) for v in gd["f"]], np.float64).reshape(shape)
+    g = np.array([float(v) for v in gd["g_hat"]], np.float64).reshape(shape)
+    res = _compare_mode(ctx, f, g, float(gd["xi"][0]), name, 1, n_steps=int(gd["n_steps"][0]))
+    assert res["iterations"] == int(gd["iterations"][0])
+    g_out, c_out, _ = ctx.correct(_dev(f), _dev(g), float(gd["xi"][0]), mode=1,
+                                  n_steps=int(gd["n_steps"][0]))
+    torch.cuda.synchronize()
+    assert g_out.cpu().numpy().ravel().tolist() == [float(v) for v in gd["g_out"]]
+    assert c_out.cpu().numpy().ravel().tolist() == [int(v) for v in gd["cnt"]]
+
+
 def test_certificate(ctx):
     from paper_2604_01397_amd import exactz
     c = synth.case_grf3d(48, seed=15, rel=1e-3)

@@ -93,3 +93,44 @@ def test_job_api_rejects_bad_requests():
         job.release()
     finally:
         ctx.close()
+
+
+def test_job_stepped_at_once_on_another_stream():
+    """A job created on one stream and stepped at once on another (no poll in
+    between) must wait for its own set-up: the result equals exz_correct."""
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = exactz.Context(0)
+    try:
+        cases = [synth.case_grf3d(48, seed=41, rel=1e-3), synth.case_grf3d(36, seed=42, rel=1e-3),
+                 synth.case_gauss2d(200, seed=43, rel=1e-3)]
+        s_create, s_step = torch.cuda.Stream(), torch.cuda.Stream()
+        jobs, ins = [], []
+        for c in cases:
+            with torch.cuda.stream(s_create):
+                f = torch.from_numpy(np.ascontiguousarray(c.f)).cuda()
+                g = torch.from_numpy(np.ascontiguousarray(c.g_hat)).cuda()
+                cnt = torch.zeros(f.shape, dtype=torch.uint8, device="cuda")
+                g_out = torch.empty_like(f)
+            s_create.synchronize()  # inputs ready; the job set-up itself stays queued
+            print("job", c.name, flush=True)
+            jobs.append(ctx.job_create(f, g, c.xi, g_out=g_out, cnt=cnt, stream=s_create))
+            ins.append((f, g))
+        # step all of them on another stream right away, with the 3D jobs
+        # in one step and the plane in its own
+        for _ in range(200):
+            ctx.step(jobs[:2], 2, stream=s_step)
+            ctx.step(jobs[2:], 2, stream=s_step)
+            if all(j.poll()[0] for j in jobs):
+                break
+        for c, j, (f, g) in zip(cases, jobs, ins):
+            done, r = j.poll()
+            assert done
+            g1, c1, r1 = ctx.correct(f, g, c.xi)
+            torch.cuda.synchronize()
+            assert torch.equal(j.g_out, g1) and torch.equal(j.cnt, c1), c.name
+            assert r["iterations"] == r1["iterations"] and r["status"] == r1["status"]
+            j.release()
+    finally:
+        ctx.close()

@@ -35,6 +35,32 @@ MUTATIONS = {
                                  "const T delta = step_size(xiT, N + 1);"),
     "descent_over_open_neighbourhood": ("  L.desc = i;\n  L.lower = 0;",
                                         "  L.desc = nb.empty() ? i : nb[0].second;\n  L.lower = 0;"),
+    # original event constraints (Sec. 4.2)
+    "c2_deleted": ("if (lt(g, R.saddles[k + 1], R.saddles[k])) mark[R.saddles[k]] = 1;",
+                   "if (false) mark[R.saddles[k]] = 1;"),
+    "c2_decreases_upper_saddle": (
+        "if (lt(g, R.saddles[k + 1], R.saddles[k])) mark[R.saddles[k]] = 1;",
+        "if (lt(g, R.saddles[k + 1], R.saddles[k])) mark[R.saddles[k + 1]] = 1;"),
+    "c3_join_deleted": ("      if (R.lc[s] >= 2) {\n        int64_t sel", "      if (false) {\n        int64_t sel"),
+    "c3_split_deleted": ("      if (R.uc[s] >= 2) {\n        int64_t sel", "      if (false) {\n        int64_t sel"),
+    "c3_join_lowers_f_choice": ("if (sel >= 0 && sel != R.mf[k]) mark[sel] = 1;",
+                                "if (sel >= 0 && sel != R.mf[k]) mark[R.mf[k]] = 1;"),
+    "c3_split_lowers_g_choice": ("if (sel >= 0 && sel != R.Mf[k]) mark[R.Mf[k]] = 1;",
+                                 "if (sel >= 0 && sel != R.Mf[k]) mark[sel] = 1;"),
+    "c3_join_lowers_lower_in_f": (
+        "if (sel >= 0 && sel != R.mf[k]) mark[sel] = 1;",
+        "if (sel >= 0 && sel != R.mf[k]) mark[lt(f, sel, R.mf[k]) ? sel : R.mf[k]] = 1;"),
+    "c3_split_lowers_lower_in_f": (
+        "if (sel >= 0 && sel != R.Mf[k]) mark[R.Mf[k]] = 1;",
+        "if (sel >= 0 && sel != R.Mf[k]) mark[lt(f, sel, R.Mf[k]) ? sel : R.Mf[k]] = 1;"),
+    "c3_join_selects_lowest_minimum_in_g": ("if (sel < 0 || lt(g, sel, t)) sel = t;",
+                                            "if (sel < 0 || lt(g, t, sel)) sel = t;"),
+    "c3_split_selects_highest_maximum_in_g": ("if (sel < 0 || lt(g, t, sel)) sel = t;",
+                                              "if (sel < 0 || lt(g, sel, t)) sel = t;"),
+    "c3_join_selects_lowest_minimum_in_f": ("if (R.mf[k] < 0 || lt(f, R.mf[k], t)) R.mf[k] = t;",
+                                            "if (R.mf[k] < 0 || lt(f, t, R.mf[k])) R.mf[k] = t;"),
+    "c3_paths_start_at_f_lower_link": ("if (glower >> p.first & 1u) {",
+                                       "if (R.lower[s] >> p.first & 1u) {"),
 }
 
 

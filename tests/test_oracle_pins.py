@@ -158,30 +158,41 @@ def test_bounds_exact(dtype):
 # worked examples
 
 
-@pytest.mark.parametrize("name", ["cascade_1d.txt", "edit_minimum_1d.txt",
-                                  "floor_collapse_1d.txt"])
+GOLDEN_RUNS = ["cascade_1d.txt", "edit_minimum_1d.txt", "floor_collapse_1d.txt",
+               "original_mode_join_c2_2d.txt", "original_mode_split_c2_2d.txt",
+               "original_mode_join_glink_2d.txt", "original_mode_split_tie_2d.txt"]
+
+
+@pytest.mark.parametrize("name", GOLDEN_RUNS)
 def test_golden_examples(golden, name):
     gd = golden(name)
     dt = np.dtype(gd["dtype"][0]).type
-    f = np.array([float(v) for v in gd["f"]], dt)
-    g = np.array([float(v) for v in gd["g_hat"]], dt)
+    shape = tuple(reversed([int(v) for v in gd["dims"]]))
+    mode = {"reformulated": oracle.REFORMULATED,
+            "original": oracle.ORIGINAL}[gd.get("mode", ["reformulated"])[0]]
+    f = np.array([float(v) for v in gd["f"]], dt).reshape(shape)
+    g = np.array([float(v) for v in gd["g_hat"]], dt).reshape(shape)
     xi = float(gd["xi"][0])
     N = int(gd["n_steps"][0])
-    g_out, cnt, st, _ = oracle.correct(f, g, xi, n_steps=N)
-    assert g_out.tolist() == [dt(float(v)) for v in gd["g_out"]]
-    assert cnt.tolist() == [int(v) for v in gd["cnt"]]
+    g_out, cnt, st, _ = oracle.correct(f, g, xi, n_steps=N, mode=mode)
+    assert g_out.ravel().tolist() == [dt(float(v)) for v in gd["g_out"]]
+    assert cnt.ravel().tolist() == [int(v) for v in gd["cnt"]]
     assert st["iterations"] == int(gd["iterations"][0])
     assert st["status"] == int(gd.get("status", ["0"])[0])
     assert st["residual_violations"] == int(gd.get("residual", ["0"])[0])
-    # per-iteration target sets
+    if "lossless" in gd:
+        assert st["lossless_vertices"] == int(gd["lossless"][0])
+    # per-iteration target sets (every iteration the fixture lists)
+    listed = [k for k in gd if k.startswith("targets_")]
+    assert all(int(k.split("_")[1]) <= st["iterations"] for k in listed)
     cur = g.copy()
     for it in range(1, st["iterations"] + 1):
         key = "targets_%d" % it
-        tg = np.nonzero(oracle.targets(f, cur))[0].tolist()
+        tg = np.nonzero(oracle.targets(f, cur, mode).ravel())[0].tolist()
         if key in gd:
             assert tg == [int(v) for v in gd[key]], it
-        cur, _, _, _ = oracle.correct(f, g, xi, n_steps=N, max_iters=it)
-    assert not oracle.targets(f, g_out).any() or st["status"] == oracle.STUCK
+        cur, _, _, _ = oracle.correct(f, g, xi, n_steps=N, mode=mode, max_iters=it)
+    assert not oracle.targets(f, g_out, mode).any() or st["status"] == oracle.STUCK
 
 
 # ----------------------------------------------------------------------------
@@ -219,6 +230,11 @@ def _check_certificates(f, g, xi, g_out, cnt, st, N, mode):
     keys = list(a) if mode == oracle.REFORMULATED else ["critical", "eg"]
     for key in keys:
         assert a[key] == b[key], key
+    if mode == oracle.ORIGINAL:
+        # C2: the saddles of f keep their order; C3: every saddle of f pairs
+        # with the same extremum as in f (the checker's own links and paths)
+        assert ck.saddle_sequence(cx, fo, go) == ck.saddle_sequence(cx, fo, fo)
+        assert ck.event_selections(cx, fo, go) == ck.event_selections(cx, fo, fo)
     # iteration bound and edit locality (reformulated mode pairs)
     if mode == oracle.REFORMULATED:
         vg = ck.vulnerability(cx, fo, gh, xiT)
