@@ -10,13 +10,18 @@ with f and g_hat already resident in HBM.
 
 Prints one JSON line.  ``roofline`` is for the dominant kernel (the check
 pass): algorithmic bytes over the check launches' device time, measured with
-HIP events on the library's stream during the timed steps.  Per vertex
-checked the method reads its value (b bytes) and f's reference (3 bytes:
-steepest-pair code and lower-link mask); per critical point also the index
-(4 bytes) and value (b bytes) of its successor in f's order.  A frontier
-pass checks only the boxes the last apply touched.
-``cpu_baseline`` is the CPU oracle, single thread, on a bounded sample of
-the same input (a 128^3 sub-block of the field, corrected to convergence).
+HIP events on the library's stream during the timed steps.  The algorithmic
+bytes of a checked vertex are those the method must move: its value (b), a
+one-byte reference code of f, one mark bit, and at a critical point the
+value of its successor in f's order (b per critical point, K of n):
+(b + 1) + 1/8 + b K / n.  A frontier pass checks only the boxes the last
+apply touched.  ``correction_frac`` prices the whole correction the same
+way: set-up (3b + 1) n, every iteration a dense pass ((b + 1) n + n/8 + b K),
+the edits (3b + 2) per target, and the sort of the critical points
+(2 (b + 4) K per 8-bit pass, b passes), over 8 TB/s and the wall time.
+``cpu_baseline`` is the CPU oracle, one thread pinned to one core, on a
+bounded sample of the same input (a 128^3 sub-block of the field, corrected
+to convergence).
 """
 from __future__ import annotations
 
@@ -30,6 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+STATUS_TEXT = {0: "converged", 1: "stuck (float floor collapse, residual violations)",
+               2: "max_iters"}
 
 
 def log(*a):
@@ -57,6 +64,32 @@ def measured_traffic(edge):
     return rec["traffic_bytes_per_launch"]
 
 
+def host_cpu():
+    """(logical CPUs this process may use, CPU model name)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), os.cpu_count(), model
+
+
+def pinned_call(fn):
+    """Run fn() with the calling thread pinned to one core (the first one this
+    process may use), then restore the affinity.  Returns (result, core)."""
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})
+    try:
+        return fn(), core
+    finally:
+        os.sched_setaffinity(0, allowed)
+
+
 def cpu_baseline(case, edge=128):
     """Time the CPU oracle on an edge^3 sub-block of the workload."""
     import numpy as np
@@ -65,13 +98,28 @@ def cpu_baseline(case, edge=128):
     f = np.ascontiguousarray(case.f[:edge, :edge, :edge])
     g = np.ascontiguousarray(case.g_hat[:edge, :edge, :edge])
     oracle.lib()
-    t0 = time.perf_counter()
-    _, _, st, _ = oracle.correct(f, g, case.xi)
-    dt = time.perf_counter() - t0
+
+    def run():
+        t0 = time.perf_counter()
+        _, _, st, _ = oracle.correct(f, g, case.xi)
+        return st, time.perf_counter() - t0
+
+    (st, dt), core = pinned_call(run)
+    allowed, total, model = host_cpu()
     return {"value": f.size * f.itemsize / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "nproc": allowed, "cpu_count": total, "cpu_model": model, "pinned_core": core,
             "sample": "%d^3 sub-block of the same field (1/%d of it), corrected to convergence "
-                      "(%d iterations) in %.1f s, one thread" % (edge, case.f.size // f.size,
-                                                                 st["iterations"], dt)}
+                      "(%d iterations) in %.1f s, one thread pinned to one core"
+                      % (edge, case.f.size // f.size, st["iterations"], dt)}
+
+
+def algorithmic_bytes(n, b, K, iterations, targets_total):
+    """Bytes the method must move for one correction (see the module text)."""
+    setup = (3 * b + 1) * n
+    per_iter = (b + 1) * n + n / 8 + b * K
+    edits = (3 * b + 2) * targets_total
+    sort = 2 * (b + 4) * K * b
+    return setup + iterations * per_iter + edits + sort
 
 
 def run_batched(torch, exactz, synth, reps=2):
@@ -259,10 +307,13 @@ def main():
     b = case.f.itemsize
     value = n * b / (ms * 1e-3) / 1e9
     avg_check_ms = check_ms / max(check_n, 1)
-    # bytes per vertex checked; critical points at their share of the field
-    per_vertex = (b + 3) + (4 + b) * res["num_critical"] / n
+    # algorithmic bytes per vertex checked; critical points at their share
+    K = res["num_critical"]
+    per_vertex = (b + 1) + 1.0 / 8 + b * K / n
     algo_bytes = per_vertex * check_v / max(check_n, 1)  # per launch, on average
     achieved = per_vertex * check_v / (check_ms * 1e-3) / 1e9
+    b_alg = algorithmic_bytes(n, b, K, res["iterations"], res["targets_total"])
+    traffic = measured_traffic(args.edge)
     line = {
         "metric": "GB/s of field corrected on 1 MI355X (plain vs batched); p50/p99 job latency",
         "value": round(value, 3),
@@ -280,14 +331,23 @@ def main():
         "config": {"workload": "plain correction, %d^3 float32 GRF k^-11/3 (seed 2), Lorenzo "
                                "quantiser, eps = 1e-4 range, N = 5, reformulated" % args.edge,
                    "n": n, "iterations": res["iterations"], "edited_vertices": res["edited_vertices"],
-                   "num_critical": res["num_critical"], "setup_ms": round(res["setup_ms"], 3),
-                   "loop_ms": round(res["loop_ms"], 3), "frontier": args.frontier},
+                   "num_critical": K, "setup_ms": round(res["setup_ms"], 3),
+                   "loop_ms": round(res["loop_ms"], 3), "frontier": args.frontier,
+                   "status": res["status"], "status_text": STATUS_TEXT.get(res["status"], "?"),
+                   "residual_violations": res["residual_violations"],
+                   "targets_total": res["targets_total"]},
         "roofline": {"bound": "hbm", "kernel": "k_check", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.edge), "avg_launch_ms": round(avg_check_ms, 5),
+                     "traffic": traffic,
+                     "traffic_over_algorithmic": (round(traffic / algo_bytes, 3)
+                                                  if traffic else None),
+                     "avg_launch_ms": round(avg_check_ms, 5),
                      "launches": check_n, "bytes_per_launch": round(algo_bytes),
-                     "bytes_per_vertex": round(per_vertex, 3),
-                     "vertices_checked_per_step": check_v // args.steps},
+                     "bytes_per_vertex": round(per_vertex, 4),
+                     "vertices_checked_per_step": check_v // args.steps,
+                     "correction_bytes": round(b_alg),
+                     "correction_roof_ms": round(b_alg / (HBM_PEAK_GBS * 1e9) * 1e3, 3),
+                     "correction_frac": round(b_alg / (HBM_PEAK_GBS * 1e9) / (ms * 1e-3), 4)},
     }
     ctx.close()
     del f, g, g_out, cnt

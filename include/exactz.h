@@ -103,6 +103,9 @@ typedef struct {
   double check_ms;             /* profiling: their summed device time */
   int64_t check_vertices;      /* profiling: vertices they checked (a
                                   frontier pass checks changed boxes only) */
+  int64_t targets_total;       /* sum over the iterations that changed a
+                                  value of |S| (targets named, blocked ones
+                                  included) */
 } exz_result;
 
 typedef struct exz_ctx exz_ctx;
@@ -133,7 +136,14 @@ exz_status exz_ctx_destroy(exz_ctx *ctx);
  *              reads a value the last apply changed: a vertex of the box or
  *              its halo, or the successor in f's order of one of its
  *              critical points (reformulated mode; default 1).  A pass that
- *              changes nothing is followed by a check of every box.
+ *              changes nothing is followed by a check of every box;
+ *   "btile3" / "btile2"  boxes of the 3D / 1D-2D members of batched calls
+ *              and of jobs created afterwards (tile_y * 100 + tile_z; 2D
+ *              boxes need tile_z = 1; 0 = 4 x 8 and 16 x 1).  A plain
+ *              "tile" also sets the 3D box of batches when "btile3" is 0;
+ *   "bgrid_box" / "bgrid_apply"  work-group caps of the batched check and
+ *              apply passes (0 = 8 resp. 16 per compute unit);
+ *   "bitem"    batched apply item size in quads per thread (1..256; 0 = 16).
  * Returns EXZ_E_INVALID for an unknown key or value. */
 exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value);
 

@@ -460,6 +460,7 @@ size_t exz_workspace_bytes(const exz_params *p) {
 static void fill_result(exz_result *r, const State &st, int status) {
   r->iterations = st.iterations;
   r->edited_vertices = st.edited_total;
+  r->targets_total = st.targets_total;
   r->edit_ops = st.edit_ops;
   r->lossless_vertices = st.lossless_total;
   r->floor_vertices = st.floor_total;

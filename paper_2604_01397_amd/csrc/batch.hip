@@ -654,6 +654,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       const State &st = hs[k];
       r.iterations = st.iterations;
       r.edited_vertices = st.edited_total;
+      r.targets_total = st.targets_total;
       r.edit_ops = st.edit_ops;
       r.lossless_vertices = st.lossless_total;
       r.floor_vertices = st.floor_total;
@@ -817,6 +818,7 @@ exz_status exz_job_poll(exz_job *job, int32_t *done, exz_result *result) {
   exz_result &r = job->result;
   r.iterations = hs.iterations;
   r.edited_vertices = hs.edited_total;
+  r.targets_total = hs.targets_total;
   r.edit_ops = hs.edit_ops;
   r.lossless_vertices = hs.lossless_total;
   r.floor_vertices = hs.floor_total;

@@ -56,6 +56,7 @@ struct State {
   int64_t lossless_total;
   int64_t floor_total;
   int64_t edited_total;
+  int64_t targets_total;          // sum of |S| over the iterations that changed a value
   int64_t residual;
   int64_t max_iters;
   int64_t passes;                 // check passes that ran (profiling)

@@ -649,6 +649,7 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
     st->lossless_total += v[2];
     st->floor_total += v[3];
     st->edited_total += v[4];
+    st->targets_total += nt;
     if (st->max_iters > 0 && st->iterations >= st->max_iters) st->done = MAXITERS;
   }
 }

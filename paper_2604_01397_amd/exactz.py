@@ -41,7 +41,8 @@ class Result(ctypes.Structure):
                 ("num_critical", ctypes.c_int64), ("status", ctypes.c_int32),
                 ("certified", ctypes.c_int32), ("setup_ms", ctypes.c_double),
                 ("loop_ms", ctypes.c_double), ("check_launches", ctypes.c_int64),
-                ("check_ms", ctypes.c_double), ("check_vertices", ctypes.c_int64)]
+                ("check_ms", ctypes.c_double), ("check_vertices", ctypes.c_int64),
+                ("targets_total", ctypes.c_int64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -31,12 +31,33 @@ def test_binding_lists_match_header():
     assert sorted(exactz.EXPORTS) == _declared()
 
 
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a header struct, as the C compiler lays it out."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "exactz.h"',
+             "int main(void) {", '  printf("%%zu\\n", sizeof(%s));' % struct]
+    for f in fields:
+        lines.append('  printf("%%zu\\n", offsetof(%s, %s));' % (struct, f))
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    return out[0], out[1:]
+
+
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
-def test_struct_layouts():
+@pytest.mark.parametrize("cls,struct", [("Params", "exz_params"), ("Result", "exz_result"),
+                                        ("Field", "exz_field")])
+def test_struct_layouts(tmp_path, cls, struct):
+    """The binding's ctypes structures match the header's layout exactly."""
     from paper_2604_01397_amd import exactz
-    assert ctypes.sizeof(exactz.Params) == 64
-    assert ctypes.sizeof(exactz.Result) == 104
-    assert ctypes.sizeof(exactz.Field) == 64 + 32
+    py = getattr(exactz, cls)
+    names = [f[0] for f in py._fields_]
+    size, offs = _c_layout(tmp_path, struct, names)
+    assert ctypes.sizeof(py) == size
+    assert [getattr(py, nm).offset for nm in names] == offs
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
