@@ -112,8 +112,15 @@ typedef struct exz_ctx exz_ctx;
 
 /* Create a context on HIP device `device` (makes it current on this
  * thread).  The context owns a device workspace that grows on demand and is
- * reused across calls.  *out is set on success. */
-exz_status exz_ctx_create(int device, exz_ctx **out);
+ * reused across calls; hbm_budget_bytes caps the device memory the context
+ * and its jobs hold at any time (0 = no cap).  A call whose workspace would
+ * exceed the cap returns EXZ_E_NOMEM and leaves earlier state intact, so a
+ * scheduler can admit work by the budget.  *out is set on success. */
+exz_status exz_ctx_create(int device, size_t hbm_budget_bytes, exz_ctx **out);
+
+/* Device bytes the context and its live jobs hold now (what the budget
+ * counts). */
+size_t exz_ctx_bytes_in_use(const exz_ctx *ctx);
 
 /* Release the context and its workspace.  NULL is accepted. */
 exz_status exz_ctx_destroy(exz_ctx *ctx);
@@ -165,6 +172,15 @@ size_t exz_workspace_bytes(const exz_params *params);
 exz_status exz_correct(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
                        uint8_t *cnt_io, const exz_params *params, exz_result *result,
                        void *stream);
+
+/* exz_correct for HOST pointers (tests, small tools): f, g_hat and the
+ * counts are copied to device buffers the context owns (they count against
+ * its budget), corrected on the default stream, and g' (and the counts if
+ * cnt_io is not NULL) copied back into g_out / cnt_io, which may alias
+ * g_hat.  The same statuses as exz_correct; on an error status g_out is
+ * left unchanged.  Timings in *result exclude the copies. */
+exz_status exz_correct_host(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
+                            uint8_t *cnt_io, const exz_params *params, exz_result *result);
 
 /* One field of a batch. */
 typedef struct {

@@ -20,23 +20,45 @@ using namespace exz;
 namespace exz {
 
 void Arena::release() {
+  if (fixed) {
+    base = end = nullptr;
+    after = nullptr;
+    cap = off = 0;
+    fixed = false;
+    return;
+  }
   if (base) (void)hipFree(base);
+  if (budget) budget->used -= cap;
   base = nullptr;
   cap = off = 0;
 }
 
 hipError_t Arena::reserve(size_t bytes) {
   off = 0;
+  if (fixed) {
+    if (after) {
+      const uintptr_t a = ((uintptr_t)after->base + after->off + 255) & ~(uintptr_t)255;
+      base = (char *)a;
+      cap = base < end ? (size_t)(end - base) : 0;
+    }
+    return bytes <= cap ? hipSuccess : hipErrorOutOfMemory;
+  }
   if (bytes <= cap) return hipSuccess;
   release();
   const size_t want = bytes + bytes / 8 + 4096;
-  hipError_t e = hipMalloc(&base, want);
+  if (budget && budget->limit && budget->used + want > budget->limit) {
+    // the slack is a convenience: fall back to the exact size before failing
+    if (budget->used + bytes > budget->limit) return hipErrorOutOfMemory;
+  }
+  const size_t got = (budget && budget->limit && budget->used + want > budget->limit) ? bytes : want;
+  hipError_t e = hipMalloc(&base, got);
   if (e != hipSuccess) {
     base = nullptr;
     (void)hipGetLastError();
     return e;
   }
-  cap = want;
+  cap = got;
+  if (budget) budget->used += got;
   return hipSuccess;
 }
 
@@ -223,7 +245,9 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   Layout LA;
   size_t oa[9];
   layout_a(fd, cnt_io == nullptr, 0, false, LA, oa);
-  HIP_OR_FAIL(A.reserve(LA.total));
+  if (A.reserve(LA.total) != hipSuccess)
+    return fail(ctx, EXZ_E_NOMEM, "%zu bytes of per-vertex workspace do not fit (%s)", LA.total,
+                A.fixed ? "static buffer" : "device memory or context budget");
   char *base = (char *)A.take(LA.total);
   fd.st = (State *)(base + oa[0]);
   fd.low = (uint16_t *)(base + oa[1]);
@@ -254,7 +278,9 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   Layout LB;
   size_t ob[12];
   layout_b(fd, K, LB, ob);
-  HIP_OR_FAIL(B.reserve(LB.total));
+  if (B.reserve(LB.total) != hipSuccess)
+    return fail(ctx, EXZ_E_NOMEM, "%zu bytes of critical-point workspace do not fit (%s)",
+                LB.total, B.fixed ? "static buffer" : "device memory or context budget");
   char *bb = (char *)B.take(LB.total);
   fd.cp_vtx = (uint32_t *)(bb + ob[1]);
   fd.cp_idx = (uint32_t *)(bb + ob[3]);
@@ -295,7 +321,9 @@ exz_status setup_paths(exz_ctx *ctx, FieldDev &fd, bool original, bool certify, 
   Layout LC;
   size_t oc[6];
   layout_c(fd, original, certify, LC, oc);
-  HIP_OR_FAIL(C.reserve(LC.total));
+  if (C.reserve(LC.total) != hipSuccess)
+    return fail(ctx, EXZ_E_NOMEM, "%zu bytes of path workspace do not fit (%s)", LC.total,
+                C.fixed ? "static buffer" : "device memory or context budget");
   char *cb = (char *)C.take(LC.total);
   fd.lab_f = (uint32_t *)(cb + oc[0]);
   fd.lab = (uint32_t *)(cb + oc[1]);
@@ -334,7 +362,7 @@ const char *exz_status_string(int status) {
 
 const char *exz_last_error(const exz_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
 
-exz_status exz_ctx_create(int device, exz_ctx **out) {
+exz_status exz_ctx_create(int device, size_t hbm_budget_bytes, exz_ctx **out) {
   if (!out) return EXZ_E_INVALID;
   *out = nullptr;
   int count = 0;
@@ -342,6 +370,17 @@ exz_status exz_ctx_create(int device, exz_ctx **out) {
   if (hipSetDevice(device) != hipSuccess) return EXZ_E_HIP;
   exz_ctx *ctx = new exz_ctx();
   ctx->device = device;
+  ctx->budget.limit = hbm_budget_bytes;
+  for (Arena *a : {&ctx->A, &ctx->B, &ctx->C, &ctx->BA, &ctx->BB, &ctx->H}) a->budget = &ctx->budget;
+  // events of the single-field driver, created here so that a correction
+  // call creates nothing
+  if (hipEventCreate(&ctx->ev_start) != hipSuccess || hipEventCreate(&ctx->ev_setup) != hipSuccess ||
+      hipEventCreate(&ctx->ev_end) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->poll_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->poll_ev[1], hipEventDisableTiming) != hipSuccess) {
+    exz_ctx_destroy(ctx);
+    return EXZ_E_HIP;
+  }
   std::vector<uint8_t> comp(1u << NSLOT);
   build_component_table(comp.data());
   std::vector<uint32_t> conn(512);
@@ -368,6 +407,7 @@ exz_status exz_ctx_destroy(exz_ctx *ctx) {
   ctx->C.release();
   ctx->BA.release();
   ctx->BB.release();
+  ctx->H.release();
   if (ctx->step_host) (void)hipHostFree(ctx->step_host);
   if (ctx->step_dev) (void)hipFree(ctx->step_dev);
   if (ctx->step_copied) (void)hipEventDestroy(ctx->step_copied);
@@ -479,10 +519,58 @@ exz_status exz_correct(exz_ctx *ctx, const void *f, const void *g_hat, void *g_o
   Busy busy(ctx);
   if (!busy.ok) return (exz_status)(res->status = fail(ctx, EXZ_E_BUSY, "context busy"));
   ctx->last_error.clear();
-  exz_status st = exz_correct_impl(ctx, f, g_hat, g_out, cnt_io, params, res, (hipStream_t)stream);
+  exz_status st = exz_correct_impl(ctx, f, g_hat, g_out, cnt_io, params, res, (hipStream_t)stream,
+                                   ctx->A, ctx->B, ctx->C, ctx->profile);
   res->status = st;
   return st;
 }
+
+exz_status exz_correct_host(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
+                            uint8_t *cnt_io, const exz_params *params, exz_result *result) {
+  exz_result dummy;
+  exz_result *res = result ? result : &dummy;
+  std::memset(res, 0, sizeof *res);
+  res->certified = -1;
+  if (!ctx) return (exz_status)(res->status = EXZ_E_INVALID);
+  Busy busy(ctx);
+  if (!busy.ok) return (exz_status)(res->status = fail(ctx, EXZ_E_BUSY, "context busy"));
+  ctx->last_error.clear();
+  if (!f || !g_hat || !g_out)
+    return (exz_status)(res->status = fail(ctx, EXZ_E_INVALID, "null field pointer"));
+  FieldDev fd;
+  exz_status st = prepare_field(ctx, params, fd);
+  if (st != EXZ_OK) return (exz_status)(res->status = st);
+  if (params->resume && !cnt_io)
+    return (exz_status)(res->status = fail(ctx, EXZ_E_INVALID, "resume needs cnt_io"));
+  if (hipSetDevice(ctx->device) != hipSuccess)
+    return (exz_status)(res->status = fail(ctx, EXZ_E_HIP, "hipSetDevice failed"));
+  // device copies: f, g (g_hat in, g' out, corrected in place), counts
+  const size_t n = (size_t)fd.n, vb = n * (fd.dtype == EXZ_F32 ? 4 : 8);
+  Layout L;
+  const size_t of = L.add(vb), og = L.add(vb), oc = L.add(n);
+  if (ctx->H.reserve(L.total) != hipSuccess)
+    return (exz_status)(res->status = fail(ctx, EXZ_E_NOMEM, "%zu bytes for the device copies "
+                                           "do not fit", L.total));
+  char *base = (char *)ctx->H.take(L.total);
+  void *df = base + of, *dg = base + og;
+  uint8_t *dc = (uint8_t *)(base + oc);
+  hipStream_t s = nullptr;
+  hipError_t e = hipMemcpy(df, f, vb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dg, g_hat, vb, hipMemcpyHostToDevice);
+  if (e == hipSuccess && params->resume) e = hipMemcpy(dc, cnt_io, n, hipMemcpyHostToDevice);
+  if (e != hipSuccess)
+    return (exz_status)(res->status = fail(ctx, EXZ_E_HIP, "copy in: %s", hipGetErrorString(e)));
+  st = exz_correct_impl(ctx, df, dg, dg, dc, params, res, s, ctx->A, ctx->B, ctx->C, ctx->profile);
+  res->status = st;
+  if (st < 0) return st;
+  e = hipMemcpy(g_out, dg, vb, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && cnt_io) e = hipMemcpy(cnt_io, dc, n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess)
+    return (exz_status)(res->status = fail(ctx, EXZ_E_HIP, "copy out: %s", hipGetErrorString(e)));
+  return st;
+}
+
+size_t exz_ctx_bytes_in_use(const exz_ctx *ctx) { return ctx ? ctx->budget.used : 0; }
 
 exz_status exz_debug_bounds(exz_ctx *ctx, int32_t dtype, const void *f, int64_t n, double xi,
                             void *L_out, void *U_out, void *stream) {
@@ -536,25 +624,20 @@ namespace exz {
 
 exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
                             uint8_t *cnt_io, const exz_params *params, exz_result *res,
-                            hipStream_t s) {
+                            hipStream_t s, Arena &A, Arena &B, Arena &C, bool profile) {
   if (!f || !g_hat || !g_out) return fail(ctx, EXZ_E_INVALID, "null field pointer");
   FieldDev fd;
   exz_status st = prepare_field(ctx, params, fd);
   if (st != EXZ_OK) return st;
   if (params->resume && !cnt_io) return fail(ctx, EXZ_E_INVALID, "resume needs cnt_io");
   HIP_OR_FAIL(hipSetDevice(ctx->device));
-  if (!ctx->ev_start) {
-    HIP_OR_FAIL(hipEventCreate(&ctx->ev_start));
-    HIP_OR_FAIL(hipEventCreate(&ctx->ev_setup));
-    HIP_OR_FAIL(hipEventCreate(&ctx->ev_end));
-  }
   HIP_OR_FAIL(hipEventRecord(ctx->ev_start, s));
-  st = setup_field(ctx, fd, f, g_hat, g_out, cnt_io, params->max_iters, ctx->A, ctx->B, s);
+  st = setup_field(ctx, fd, f, g_hat, g_out, cnt_io, params->max_iters, A, B, s);
   if (st != EXZ_OK) return st;
   res->num_critical = fd.K;
   uint32_t *lab_g = nullptr;
   st = setup_paths(ctx, fd, params->event_mode == EXZ_EVENT_ORIGINAL, params->certify != 0,
-                   ctx->C, &lab_g, s);
+                   C, &lab_g, s);
   if (st != EXZ_OK) return st;
   HIP_OR_FAIL(hipEventRecord(ctx->ev_setup, s));
 
@@ -570,14 +653,10 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   int64_t issued = 0;
   size_t ev_used = 0;
-  if (!ctx->poll_ev[0]) {
-    HIP_OR_FAIL(hipEventCreateWithFlags(&ctx->poll_ev[0], hipEventDisableTiming));
-    HIP_OR_FAIL(hipEventCreateWithFlags(&ctx->poll_ev[1], hipEventDisableTiming));
-  }
   auto issue_chunk = [&](int slot) -> exz_status {
     for (int k = 0; k < chunk; ++k) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (ctx->profile) {
+      if (profile) {
         while (ctx->events.size() < ev_used + 2) {
           hipEvent_t e;
           HIP_OR_FAIL(hipEventCreate(&e));
@@ -626,7 +705,7 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
   if (hs.done == STUCK) status = EXZ_W_STUCK;
   if (hs.done == MAXITERS) status = EXZ_W_MAX_ITERS;
   fill_result(res, hs, status);
-  if (ctx->profile) {
+  if (profile) {
     // every check launch issued, those past the fixpoint included (they
     // return at once), so the average matches a kernel trace of the call
     const int64_t launched = (int64_t)(ev_used / 2);

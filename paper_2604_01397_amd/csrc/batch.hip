@@ -701,6 +701,7 @@ exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, ex
   HIP_OR_FAIL_B(hipSetDevice(ctx->device));
   exz_job *job = new exz_job();
   job->ctx = ctx;
+  job->A.budget = job->B.budget = &ctx->budget;  // the job's workspace counts against the budget
   job->params = field->params;
   std::memset(&job->result, 0, sizeof job->result);
   job->result.certified = -1;

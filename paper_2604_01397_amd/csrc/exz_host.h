@@ -10,14 +10,44 @@
 
 namespace exz {
 
-// Growable device buffer carved into 256-byte aligned pieces per call.
+// Device bytes a context may hold (arenas of the context and of its jobs);
+// limit 0 = no limit.
+struct Budget {
+  size_t limit = 0;
+  size_t used = 0;
+};
+
+// Growable device buffer carved into 256-byte aligned pieces per call.  A
+// fixed arena uses memory it does not own (the no-allocation entry point's
+// static buffer): it never allocates or frees, and a reserve beyond its
+// capacity fails with hipErrorOutOfMemory.  A fixed arena chained after
+// another one starts, at each reserve, where that one's carving ends.
 struct Arena {
   char *base = nullptr;
   size_t cap = 0;
   size_t off = 0;
+  bool fixed = false;
+  char *end = nullptr;          // fixed: end of the usable memory
+  const Arena *after = nullptr; // fixed: start after this arena's carving
+  Budget *budget = nullptr;     // charged for what this arena allocates
   hipError_t reserve(size_t bytes);  // resets the carve offset
   void *take(size_t bytes);
   void release();
+  void wrap(void *p, size_t bytes) {
+    base = (char *)p;
+    end = base + bytes;
+    cap = bytes;
+    off = 0;
+    fixed = true;
+    after = nullptr;
+  }
+  void chain(const Arena *prev, char *limit) {
+    base = nullptr;
+    end = limit;
+    cap = off = 0;
+    fixed = true;
+    after = prev;
+  }
 };
 
 // Size accounting that mirrors Arena::take.
@@ -31,7 +61,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
                        uint8_t *cnt_io, int64_t max_iters, Arena &A, Arena &B, hipStream_t s);
 exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
                             uint8_t *cnt_io, const exz_params *params, exz_result *res,
-                            hipStream_t s);
+                            hipStream_t s, Arena &A, Arena &B, Arena &C, bool profile);
 // f and g 16-byte aligned and the counts 4-byte aligned (apply may then
 // read a quad of vertices with vector loads).
 inline int quad_aligned(const FieldDev &fd) {
@@ -71,6 +101,8 @@ struct exz_ctx {
   int grid_blocks = -1;
   bool frontier = true;
   std::string last_error;
+  exz::Budget budget;               // device bytes of the context and its jobs
+  exz::Arena H;                     // device copies for exz_correct_host
   uint8_t *d_comp = nullptr;        // link component table (2^14 bytes)
   uint32_t *d_conn = nullptr;       // one-component bits (2^14 bits)
   exz::State *h_state = nullptr;    // pinned

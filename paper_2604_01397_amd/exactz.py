@@ -19,10 +19,10 @@ OK, W_STUCK, W_MAX_ITERS = 0, 1, 2
 E_INVALID, E_NONFINITE, E_BOUND, E_NOMEM, E_HIP, E_BUSY = -1, -2, -3, -4, -5, -6
 
 EXPORTS = (
-    "exz_ctx_create", "exz_ctx_destroy", "exz_ctx_set_option", "exz_workspace_bytes",
-    "exz_correct", "exz_correct_batch", "exz_job_create", "exz_step", "exz_job_poll",
-    "exz_job_release", "exz_job_bytes", "exz_status_string", "exz_last_error",
-    "exz_debug_bounds", "exz_debug_targets",
+    "exz_ctx_create", "exz_ctx_destroy", "exz_ctx_set_option", "exz_ctx_bytes_in_use",
+    "exz_workspace_bytes", "exz_correct", "exz_correct_host", "exz_correct_batch",
+    "exz_job_create", "exz_step", "exz_job_poll", "exz_job_release", "exz_job_bytes",
+    "exz_status_string", "exz_last_error", "exz_debug_bounds", "exz_debug_targets",
 )
 
 
@@ -72,7 +72,10 @@ def load(path: str | None = None):
         raise ImportError("libexactz.so not built: run __graft_entry__.build() (expected %s)" % path)
     L = ctypes.CDLL(path)
     p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
-    L.exz_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(p)]
+    L.exz_ctx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(p)]
+    L.exz_ctx_bytes_in_use.argtypes = [p]
+    L.exz_ctx_bytes_in_use.restype = ctypes.c_size_t
+    L.exz_correct_host.argtypes = [p, p, p, p, p, ctypes.POINTER(Params), ctypes.POINTER(Result)]
     L.exz_ctx_destroy.argtypes = [p]
     L.exz_ctx_set_option.argtypes = [p, ctypes.c_char_p, i64]
     L.exz_workspace_bytes.argtypes = [ctypes.POINTER(Params)]
@@ -92,6 +95,7 @@ def load(path: str | None = None):
     L.exz_debug_bounds.argtypes = [p, i32, p, i64, ctypes.c_double, p, p, p]
     L.exz_debug_targets.argtypes = [p, p, p, ctypes.POINTER(Params), p, ctypes.POINTER(i64), p]
     for name in ("exz_ctx_create", "exz_ctx_destroy", "exz_ctx_set_option", "exz_correct",
+                 "exz_correct_host",
                  "exz_correct_batch", "exz_job_create", "exz_step", "exz_job_poll",
                  "exz_job_release", "exz_debug_bounds", "exz_debug_targets"):
         getattr(L, name).restype = ctypes.c_int
@@ -141,12 +145,16 @@ def _check_tensor(t, like=None):
 
 
 class Context:
-    """A library context on one device (owns the device workspace)."""
+    """A library context on one device (owns the device workspace).
 
-    def __init__(self, device: int = 0, **options):
+    ``budget`` caps the device bytes the context and its jobs may hold
+    (0 = no cap); a call that would exceed it raises with E_NOMEM.
+    """
+
+    def __init__(self, device: int = 0, budget: int = 0, **options):
         self.lib = load()
         h = ctypes.c_void_p()
-        st = self.lib.exz_ctx_create(int(device), ctypes.byref(h))
+        st = self.lib.exz_ctx_create(int(device), int(budget), ctypes.byref(h))
         if st != OK:
             raise ExactzError(st, "exz_ctx_create failed")
         self.h = h
@@ -161,6 +169,10 @@ class Context:
 
     def last_error(self):
         return (self.lib.exz_last_error(self.h) or b"").decode()
+
+    def bytes_in_use(self):
+        """Device bytes the context and its live jobs hold (what the budget counts)."""
+        return int(self.lib.exz_ctx_bytes_in_use(self.h))
 
     def close(self):
         if self.h:
@@ -200,6 +212,33 @@ class Context:
                                   ctypes.c_void_p(g_out.data_ptr()),
                                   ctypes.c_void_p(cnt.data_ptr()), ctypes.byref(p),
                                   ctypes.byref(r), _stream_ptr(stream))
+        if st < 0 and raise_on_error:
+            raise ExactzError(st, self.last_error())
+        return g_out, cnt, r.to_dict()
+
+    def correct_host(self, f, g_hat, xi, n_steps=5, mode=REFORMULATED, max_iters=0,
+                     certify=False, cnt=None, resume=False, raise_on_error=True):
+        """exz_correct_host on numpy arrays: returns (g_out, cnt, result dict)."""
+        import numpy as np
+        f = np.ascontiguousarray(f)
+        g_hat = np.ascontiguousarray(g_hat)
+        if f.dtype not in (np.float32, np.float64) or g_hat.dtype != f.dtype or g_hat.shape != f.shape:
+            raise ValueError("f and g_hat must be float32/float64 arrays of one shape")
+        g_out = np.empty_like(f)
+        if cnt is None:
+            cnt = np.zeros(f.shape, np.uint8)
+        cnt = np.ascontiguousarray(cnt, dtype=np.uint8).copy()
+        p = Params()
+        p.ndim = f.ndim
+        p.dtype = F32 if f.dtype == np.float32 else F64
+        dims = list(reversed(f.shape)) + [1] * (3 - f.ndim)
+        for k in range(3):
+            p.dims[k] = int(dims[k])
+        p.xi, p.n_steps, p.event_mode = float(xi), int(n_steps), int(mode)
+        p.max_iters, p.certify, p.resume = int(max_iters), int(bool(certify)), int(bool(resume))
+        r = Result()
+        st = self.lib.exz_correct_host(self.h, f.ctypes.data, g_hat.ctypes.data, g_out.ctypes.data,
+                                       cnt.ctypes.data, ctypes.byref(p), ctypes.byref(r))
         if st < 0 and raise_on_error:
             raise ExactzError(st, self.last_error())
         return g_out, cnt, r.to_dict()
