@@ -182,6 +182,22 @@ exz_status exz_correct(exz_ctx *ctx, const void *f, const void *g_hat, void *g_o
 exz_status exz_correct_host(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
                             uint8_t *cnt_io, const exz_params *params, exz_result *result);
 
+/* exz_correct for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, statuses and results as exz_correct (bit for bit), but the
+ * call allocates nothing: its workspace is one static device buffer of
+ * 128 MiB per GPU, held until the process ends, that every call on that GPU
+ * shares.  A field whose workspace does not fit (about 14 bytes per vertex
+ * plus 28 (float32) or 40 (float64) bytes per critical point, path
+ * workspace for the original mode or the certificate on top) returns
+ * EXZ_E_NOMEM with a message; the per-vertex part is checked before any work
+ * is issued.  The caller passes f, g_hat, g_out (and cnt_io) as for
+ * exz_correct.  Calls that overlap in time on the same GPU race on the
+ * buffer: serialise them.  Profiling counters are not recorded. */
+exz_status exz_correct_noalloc(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
+                               uint8_t *cnt_io, const exz_params *params, exz_result *result,
+                               void *stream);
+
 /* One field of a batch. */
 typedef struct {
   exz_params params;

@@ -377,7 +377,8 @@ exz_status exz_ctx_create(int device, size_t hbm_budget_bytes, exz_ctx **out) {
   if (hipEventCreate(&ctx->ev_start) != hipSuccess || hipEventCreate(&ctx->ev_setup) != hipSuccess ||
       hipEventCreate(&ctx->ev_end) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->poll_ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->poll_ev[1], hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->poll_ev[1], hipEventDisableTiming) != hipSuccess ||
+      scratch_lookup(device, &ctx->scratch, &ctx->scratch_bytes) != hipSuccess) {
     exz_ctx_destroy(ctx);
     return EXZ_E_HIP;
   }

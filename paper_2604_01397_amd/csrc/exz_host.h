@@ -62,6 +62,9 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
 exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
                             uint8_t *cnt_io, const exz_params *params, exz_result *res,
                             hipStream_t s, Arena &A, Arena &B, Arena &C, bool profile);
+// Device address of exz_correct_noalloc's static buffer on `device` (which
+// the caller has made current), looked up once per device; its size.
+hipError_t scratch_lookup(int device, void **ptr, size_t *bytes);
 // f and g 16-byte aligned and the counts 4-byte aligned (apply may then
 // read a quad of vertices with vector loads).
 inline int quad_aligned(const FieldDev &fd) {
@@ -103,6 +106,8 @@ struct exz_ctx {
   std::string last_error;
   exz::Budget budget;               // device bytes of the context and its jobs
   exz::Arena H;                     // device copies for exz_correct_host
+  void *scratch = nullptr;          // exz_correct_noalloc's buffer on this device
+  size_t scratch_bytes = 0;
   uint8_t *d_comp = nullptr;        // link component table (2^14 bytes)
   uint32_t *d_conn = nullptr;       // one-component bits (2^14 bits)
   exz::State *h_state = nullptr;    // pinned

@@ -20,7 +20,8 @@ E_INVALID, E_NONFINITE, E_BOUND, E_NOMEM, E_HIP, E_BUSY = -1, -2, -3, -4, -5, -6
 
 EXPORTS = (
     "exz_ctx_create", "exz_ctx_destroy", "exz_ctx_set_option", "exz_ctx_bytes_in_use",
-    "exz_workspace_bytes", "exz_correct", "exz_correct_host", "exz_correct_batch",
+    "exz_workspace_bytes", "exz_correct", "exz_correct_host", "exz_correct_noalloc",
+    "exz_correct_batch",
     "exz_job_create", "exz_step", "exz_job_poll", "exz_job_release", "exz_job_bytes",
     "exz_status_string", "exz_last_error", "exz_debug_bounds", "exz_debug_targets",
 )
@@ -76,6 +77,8 @@ def load(path: str | None = None):
     L.exz_ctx_bytes_in_use.argtypes = [p]
     L.exz_ctx_bytes_in_use.restype = ctypes.c_size_t
     L.exz_correct_host.argtypes = [p, p, p, p, p, ctypes.POINTER(Params), ctypes.POINTER(Result)]
+    L.exz_correct_noalloc.argtypes = [p, p, p, p, p, ctypes.POINTER(Params),
+                                      ctypes.POINTER(Result), p]
     L.exz_ctx_destroy.argtypes = [p]
     L.exz_ctx_set_option.argtypes = [p, ctypes.c_char_p, i64]
     L.exz_workspace_bytes.argtypes = [ctypes.POINTER(Params)]
@@ -95,7 +98,7 @@ def load(path: str | None = None):
     L.exz_debug_bounds.argtypes = [p, i32, p, i64, ctypes.c_double, p, p, p]
     L.exz_debug_targets.argtypes = [p, p, p, ctypes.POINTER(Params), p, ctypes.POINTER(i64), p]
     for name in ("exz_ctx_create", "exz_ctx_destroy", "exz_ctx_set_option", "exz_correct",
-                 "exz_correct_host",
+                 "exz_correct_host", "exz_correct_noalloc",
                  "exz_correct_batch", "exz_job_create", "exz_step", "exz_job_poll",
                  "exz_job_release", "exz_debug_bounds", "exz_debug_targets"):
         getattr(L, name).restype = ctypes.c_int
@@ -212,6 +215,33 @@ class Context:
                                   ctypes.c_void_p(g_out.data_ptr()),
                                   ctypes.c_void_p(cnt.data_ptr()), ctypes.byref(p),
                                   ctypes.byref(r), _stream_ptr(stream))
+        if st < 0 and raise_on_error:
+            raise ExactzError(st, self.last_error())
+        return g_out, cnt, r.to_dict()
+
+    def correct_noalloc(self, f, g_hat, xi, n_steps=5, mode=REFORMULATED, max_iters=0,
+                        certify=False, g_out=None, cnt=None, resume=False, stream=None,
+                        raise_on_error=True):
+        """exz_correct_noalloc: like correct(), but the library allocates nothing
+        (its workspace is a static per-GPU buffer); the caller's tensors are
+        allocated here, before the call."""
+        import torch
+        _check_tensor(f)
+        _check_tensor(g_hat, f)
+        if g_out is None:
+            g_out = torch.empty_like(f)
+        _check_tensor(g_out, f)
+        if cnt is None:
+            cnt = torch.zeros(f.shape, dtype=torch.uint8, device=f.device)
+        elif cnt.dtype != torch.uint8 or cnt.shape != f.shape:
+            raise ValueError("cnt must be uint8 of f's shape")
+        p = make_params(f, xi, n_steps, mode, max_iters, certify, resume)
+        r = Result()
+        st = self.lib.exz_correct_noalloc(self.h, ctypes.c_void_p(f.data_ptr()),
+                                          ctypes.c_void_p(g_hat.data_ptr()),
+                                          ctypes.c_void_p(g_out.data_ptr()),
+                                          ctypes.c_void_p(cnt.data_ptr()), ctypes.byref(p),
+                                          ctypes.byref(r), _stream_ptr(stream))
         if st < 0 and raise_on_error:
             raise ExactzError(st, self.last_error())
         return g_out, cnt, r.to_dict()
