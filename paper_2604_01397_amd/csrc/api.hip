@@ -205,7 +205,7 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
   off[2] = L.add(8 * (size_t)fd.nchunk);                     // cpbits
   off[3] = L.add(4 * ((size_t)fd.nchunk + 1));               // cpoff
   off[4] = L.add(mark_bytes(fd));                            // target marks + zero padding
-  off[5] = L.add(8 * n);                                     // succ, pred_box
+  off[5] = 0;
   off[6] = own_cnt ? L.add(n) : 0;                           // cnt
   off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
   // dirty box flags, sized for the smallest box (64 x 1 x 1) so the
@@ -220,11 +220,11 @@ void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]) {
   const size_t b = fd.dtype == 0 ? 4 : 8;
   const size_t kb = b;  // sort key bytes
   const uint32_t Kc = K ? K : 1;
-  off[0] = 0;
+  off[0] = L.add(4 * (size_t)Kc + 4 * (((size_t)Kc + 31) / 32));  // cp_rank, cp_below
   off[1] = L.add(4 * (size_t)Kc);  // cp_vtx
   off[2] = 0;
   off[3] = L.add(4 * (size_t)Kc);  // cp_idx
-  off[4] = L.add(b * Kc);          // cpv
+  off[4] = L.add(b * Kc);          // cpr
   off[5] = L.add(kb * Kc);         // keys
   off[6] = L.add(kb * Kc);         // keys tmp
   off[7] = L.add(4 * (size_t)Kc);  // vals
@@ -256,8 +256,6 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   fd.cpoff = (uint32_t *)(base + oa[3]);
   fd.tmark = (uint8_t *)(base + oa[4]);
   fd.bdirty = (uint8_t *)(base + oa[8]);
-  fd.succ = (uint32_t *)(base + oa[5]);
-  fd.pred_box = fd.succ + fd.n;
   fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
   fd.vec = quad_aligned(fd);
   uint32_t *scan_tmp = (uint32_t *)(base + oa[7]);
@@ -282,9 +280,11 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
     return fail(ctx, EXZ_E_NOMEM, "%zu bytes of critical-point workspace do not fit (%s)",
                 LB.total, B.fixed ? "static buffer" : "device memory or context budget");
   char *bb = (char *)B.take(LB.total);
+  fd.cp_rank = (uint32_t *)(bb + ob[0]);
+  fd.cp_below = fd.cp_rank + (K ? K : 1);
   fd.cp_vtx = (uint32_t *)(bb + ob[1]);
   fd.cp_idx = (uint32_t *)(bb + ob[3]);
-  fd.cpv = bb + ob[4];
+  fd.cpr = bb + ob[4];
   void *keys = bb + ob[5];
   void *keys_tmp = bb + ob[6];
   uint32_t *vals = (uint32_t *)(bb + ob[7]);
@@ -297,7 +297,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
     HIP_OR_FAIL(launch_iota(vals, K, s));
     HIP_OR_FAIL(launch_radix_sort(fd.dtype == 0 ? 4 : 8, keys, vals, keys_tmp, vals_tmp, K, hist,
                                   stmp, scan_tmp_words((uint32_t)(hw - 1)), s));
-    HIP_OR_FAIL(launch_cp_init(fd, vals, (uint32_t *)keys_tmp, s));
+    HIP_OR_FAIL(launch_cp_init(fd, vals, s));
   }
   return EXZ_OK;
 }

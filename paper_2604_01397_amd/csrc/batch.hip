@@ -113,6 +113,29 @@ __global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *__r
   if (nf) flush_counts<APPLY_BLOCK / 64>(fields[field[kc]].st, ec, blockIdx.x);
 }
 
+// Order passes (reformulated event constraints): field k owns items
+// [base[k], base[k+1]), one per ORD_ITEM ranks of its critical points.
+constexpr uint32_t ORD_ITEM = 16 * 256;
+__global__ void __launch_bounds__(256) k_order_batch(const FieldDev *__restrict__ fields,
+                                                     const uint32_t *__restrict__ lists) {
+  const uint32_t nf = lists[0], total = lists[1];
+  const uint32_t *field = lists + 2, *base = lists + 2 + nf;
+  uint32_t k = 0;
+  for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+    k = next_field_uniform(base, nf, it, k);
+    const FieldDev &fd = fields[__builtin_amdgcn_readfirstlane(field[k])];
+    if (fd.st->done) continue;
+    const uint32_t r0 = (it - base[k]) * ORD_ITEM;
+    const uint32_t lim = min((uint32_t)fd.K, r0 + ORD_ITEM + 1);  // the item's pairs only
+    for (uint32_t j = 0; j < ORD_ITEM && r0 + j + 1 < lim; j += 1024) {
+      if (fd.dtype == 0)
+        order_quad<float>(fd, r0 + j + 4 * threadIdx.x, lim, __lane_id() != 63);
+      else
+        order_quad<double>(fd, r0 + j + 4 * threadIdx.x, lim, __lane_id() != 63);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(64) k_finalize_batch(const FieldDev *fields, const uint32_t *lists) {
   const uint32_t nf = lists[0];
   if (blockIdx.x < nf) finalize_field(fields[lists[2 + blockIdx.x]]);
@@ -241,7 +264,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
 // Device list buffers, capacity per list 2 + 2*nf + 1 words: boxes of 3D
 // float32 / 3D float64 / 2D-1D float32 / 2D-1D float64 fields, finalize (one
 // item per field), apply chunks.
-enum { L_BOX3F, L_BOX3D, L_BOX2F, L_BOX2D, L_FIN, L_APPLY, NLISTS };
+enum { L_BOX3F, L_BOX3D, L_BOX2F, L_BOX2D, L_FIN, L_APPLY, L_ORD, NLISTS };
 static size_t list_words(size_t nf) { return 2 + 2 * nf + 1; }
 
 namespace exz {
@@ -260,15 +283,16 @@ static void box_launch_check(int ty, int tz, const FieldDev *fields, const uint3
 // Issue `iters` batched iterations.
 static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dlists, size_t lw,
                              const BatchShape &shape, int iters, int grid_box,
-                             int grid_fin, int grid_apply, hipStream_t s) {
+                             int grid_fin, int grid_apply, int grid_ord, hipStream_t s) {
   const uint32_t item_quads = shape.item_quads;
   auto list = [&](int q) { return dlists + q * lw; };
-  uint32_t *lf = list(L_FIN), *la = list(L_APPLY);
+  uint32_t *lf = list(L_FIN), *la = list(L_APPLY), *lo = list(L_ORD);
   for (int it = 0; it < iters; ++it) {
     box_launch_check<float>(shape.ty3, shape.tz3, fields, list(L_BOX3F), ctx->d_conn, grid_box, s);
     box_launch_check<double>(shape.ty3, shape.tz3, fields, list(L_BOX3D), ctx->d_conn, grid_box, s);
     box_launch_check<float>(shape.ty2, shape.tz2, fields, list(L_BOX2F), ctx->d_conn, grid_box, s);
     box_launch_check<double>(shape.ty2, shape.tz2, fields, list(L_BOX2D), ctx->d_conn, grid_box, s);
+    hipLaunchKernelGGL(k_order_batch, dim3(grid_ord), dim3(256), 0, s, fields, lo);
     hipLaunchKernelGGL(k_apply_batch, dim3(grid_apply), dim3(APPLY_BLOCK), 0, s, fields, la,
                        item_quads);
     hipLaunchKernelGGL(k_finalize_batch, dim3(grid_fin), dim3(64), 0, s, fields, lf);
@@ -295,6 +319,10 @@ static void build_lists(const std::vector<const FieldDev *> &fds, const std::vec
     n[L_FIN].push_back(1);
     f[L_APPLY].push_back(idx);
     n[L_APPLY].push_back(apply_items(fd, item_quads));
+    if (fd.mode != 1 && fd.K > 1) {
+      f[L_ORD].push_back(idx);
+      n[L_ORD].push_back(((uint32_t)fd.K - 1 + ORD_ITEM - 1) / ORD_ITEM);
+    }
   }
   for (int q = 0; q < NLISTS; ++q) {
     Lists L;
@@ -332,13 +360,15 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   HIP_OR_FAIL_B(hipHostMalloc((void **)&hstates, std::max<size_t>(nf, 1) * sizeof(State),
                               hipHostMallocDefault));
   // persistent grids: enough blocks to fill the chip, never more than items
-  uint64_t max_boxes = 0, max_apply = 0;
+  uint64_t max_boxes = 0, max_apply = 0, max_ord = 0;
   for (auto &m : members) {
     max_boxes += (uint64_t)m.fd.ntiles;
     max_apply += apply_items(m.fd, shape.item_quads);
+    max_ord += ((uint64_t)m.fd.K + ORD_ITEM - 1) / ORD_ITEM;
   }
   const int grid_box = batch_grid(max_boxes, shape.grid_box, 8);
   const int grid_apply = batch_grid(max_apply, shape.grid_apply, 16);
+  const int grid_ord = batch_grid(max_ord, 0, 8);
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   hipGraphExec_t exec = nullptr;
   int exec_chunk = 0;
@@ -364,7 +394,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
         hipGraph_t graph = nullptr;
         HIP_OR_FAIL_B(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_fin,
-                         grid_apply, s);
+                         grid_apply, grid_ord, s);
         const hipError_t ce = hipStreamEndCapture(s, &graph);  // always ends the capture
         HIP_OR_FAIL_B(ce);
         const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -375,7 +405,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
       HIP_OR_FAIL_B(hipGraphLaunch(exec, s));
     } else {
       issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_fin,
-                         grid_apply, s);
+                         grid_apply, grid_ord, s);
       HIP_OR_FAIL_B(hipGetLastError());
     }
     // the members' states are consecutive (one array, slot k = member k)
@@ -541,8 +571,6 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.cpoff = (uint32_t *)(b + oa[k][3]);
       fd.tmark = (uint8_t *)(b + oa[k][4]);
       fd.bdirty = (uint8_t *)(b + oa[k][8]);
-      fd.succ = (uint32_t *)(b + oa[k][5]);
-      fd.pred_box = fd.succ + fd.n;
       uint8_t *cnt_io = fields[mem[k].index].cnt_io;
       fd.cnt = cnt_io ? cnt_io : (uint8_t *)(b + oa[k][6]);
       fd.vec = quad_aligned(fd);
@@ -595,10 +623,12 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       if (!m.active) continue;
       FieldDev &fd = m.fd;
       char *b = Bm + baseB[k];
+      const uint32_t K = (uint32_t)fd.K;
+      fd.cp_rank = (uint32_t *)(b + ob[k][0]);
+      fd.cp_below = fd.cp_rank + (K ? K : 1);
       fd.cp_vtx = (uint32_t *)(b + ob[k][1]);
       fd.cp_idx = (uint32_t *)(b + ob[k][3]);
-      fd.cpv = b + ob[k][4];
-      const uint32_t K = (uint32_t)fd.K;
+      fd.cpr = b + ob[k][4];
       if (K > 0) {
         const size_t hw = radix_hist_words(K);
         HIP_OR_FAIL_B(launch_cp_compact(fd, ctx->d_comp, b + ob[k][5], sk));
@@ -607,7 +637,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
                                         b + ob[k][6], (uint32_t *)(b + ob[k][8]), K,
                                         (uint32_t *)(b + ob[k][9]), (uint32_t *)(b + ob[k][10]),
                                         scan_tmp_words((uint32_t)(hw - 1)), sk));
-        HIP_OR_FAIL_B(launch_cp_init(fd, (uint32_t *)(b + ob[k][7]), (uint32_t *)(b + ob[k][6]), sk));
+        HIP_OR_FAIL_B(launch_cp_init(fd, (uint32_t *)(b + ob[k][7]), sk));
       }
       host_fd[k] = fd;
     }
@@ -774,7 +804,7 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
       return fail_b(ctx, EXZ_E_INVALID, "jobs of one step must share their box shape");
     }
   }
-  uint64_t boxes = 0, words = 0;
+  uint64_t boxes = 0, words = 0, ords = 0;
   std::vector<const FieldDev *> fds(nf);
   std::vector<bool> act(nf, true);
   // Stream order: this step starts after the previous step (which read the
@@ -793,6 +823,7 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
     fds[k] = &hf[k];
     words += apply_items(fd, shape.item_quads);
     boxes += (uint64_t)fd.ntiles;
+    ords += ((uint64_t)fd.K + ORD_ITEM - 1) / ORD_ITEM;
     job->last = s;
   }
   build_lists(fds, act, shape.item_quads, hl, lw);
@@ -802,7 +833,8 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   HIP_OR_FAIL_B(hipEventRecord(ctx->step_copied, s));
   const int grid_box = batch_grid(boxes, shape.grid_box, 8);
   const int grid_apply = batch_grid(words, shape.grid_apply, 16);
-  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, (int)nf, grid_apply, s);
+  const int grid_ord = batch_grid(ords, 0, 8);
+  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, (int)nf, grid_apply, grid_ord, s);
   HIP_OR_FAIL_B(hipGetLastError());
   HIP_OR_FAIL_B(hipEventRecord(ctx->step_done, s));
   return EXZ_OK;

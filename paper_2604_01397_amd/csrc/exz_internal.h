@@ -28,8 +28,6 @@ constexpr int DZS[NSLOT] = {0, 0, 0, 0, 0, 0, +1, -1, +1, -1, +1, -1, +1, -1};
 constexpr uint32_t LOW_SADDLE = 1u << 15;
 constexpr uint32_t LOW_MASK = 0x3FFFu;
 constexpr uint32_t NONE = 0xFFFFFFFFu;  // no vertex / no box
-constexpr uint32_t SUCC_SLOT = 0x7FFFFFFFu;
-constexpr uint32_t SUCC_BELOW = 0x80000000u;
 
 enum Done : int32_t { RUNNING = 0, CONVERGED = 1, STUCK = 2, MAXITERS = 3 };
 constexpr int MAX_JUMP_ROUNDS = 34;  // pointer jumping over < 2^32 labels
@@ -93,12 +91,10 @@ struct FieldDev {
   unsigned long long *cpbits;
   uint32_t *cpoff;      // nchunk + 1 exclusive prefix counts
   uint32_t *cp_vtx;     // K, vertex order -> vertex
-  uint32_t *succ;       // n: SUCC_SLOT bits: vertex-order slot of the next critical point
-                        // of f in f's order, SUCC_BELOW: its index is below this one's;
-                        // NONE for the last critical point and for other vertices
-  uint32_t *pred_box;   // n: for a critical point of f, the box holding the previous one in
-                        // f's order (NONE for the first); undefined for other vertices
-  void *cpv;            // K: current value of every critical point of f, in vertex order
+  uint32_t *cp_rank;    // K, vertex order: rank in f's order
+  uint32_t *cp_below;   // (K + 31) / 32 words, bit r: the critical point of rank r + 1 has the
+                        // lower vertex index of the pair (r, r + 1)
+  void *cpr;            // K: current value of every critical point of f, in f's order
   uint32_t *cp_idx;     // K, rank -> vertex
   uint32_t *sad_rank;   // saddle order -> rank in the CP order (K capacity)
   uint32_t *sel_f;      // 2 per critical point, in vertex order: selections in f (join,
@@ -274,9 +270,7 @@ hipError_t launch_radix_sort(int key_bytes, void *keys, uint32_t *vals, void *ke
                              uint32_t *vals_tmp, uint32_t count, uint32_t *hist, uint32_t *scan_tmp,
                              size_t scan_words, hipStream_t s);
 size_t radix_hist_words(uint32_t count);
-// box_r: K words of scratch (the sort's spare key buffer serves).
-hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, uint32_t *box_r,
-                          hipStream_t s);
+hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, hipStream_t s);
 bool box_supported(int tile_y, int tile_z);
 hipError_t launch_state_reset(const FieldDev &fd, int64_t max_iters, hipStream_t s);
 hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,

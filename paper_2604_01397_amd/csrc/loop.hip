@@ -122,6 +122,16 @@ __global__ void __launch_bounds__(64 * TY) k_ref(FieldDev fd, const uint32_t *__
   }
 }
 
+// Reformulated event constraints: every pair of consecutive critical points
+// of f, in f's order.
+template <class T>
+__global__ void __launch_bounds__(256) k_order(FieldDev fd) {
+  if (fd.st->done) return;
+  const uint32_t K = (uint32_t)fd.K;
+  for (uint32_t b = blockIdx.x * 1024u; b + 1 < K; b += gridDim.x * 1024u)
+    order_quad<T>(fd, b + 4u * threadIdx.x, K, __lane_id() != 63);
+}
+
 // ApplyBoundedEdits over the target marks.
 template <class T>
 __global__ void __launch_bounds__(APPLY_BLOCK) k_apply(FieldDev fd) {
@@ -187,7 +197,12 @@ static void launch_check_events(const FieldDev &fd, const uint32_t *conn, const 
   EXZ_BOX_SHAPES(EXZ_BOX_CHECK)
 #undef EXZ_BOX_CHECK
   if (ev1) (void)hipEventRecord(ev1, s);
-  if (fd.mode == 1) (void)launch_original_events(fd, comp, s);
+  if (fd.mode == 1) {
+    (void)launch_original_events(fd, comp, s);
+  } else if (fd.K > 1) {
+    const int g = (int)std::min<uint32_t>(((uint32_t)fd.K + 1022) / 1024, 16384u);
+    hipLaunchKernelGGL(k_order<T>, dim3(g), dim3(256), 0, s, fd);
+  }
 }
 
 template <class T>

@@ -45,8 +45,39 @@ template <> __device__ __forceinline__ double outside_value<double>() {
 // rows.  Rows outside the domain, and cells left or right of it, are
 // staged as outside_value().  All loads of a thread are issued before the
 // first LDS write.
-template <int TY, int TZ, class V>
-__device__ __forceinline__ void stage_rows(const FieldDev &fd, const V *__restrict__ src, V *S,
+// Conversion of a staged cell: the value itself ...
+struct AsIs {
+  template <class V> static __device__ __forceinline__ V conv(V v, uint32_t) { return v; }
+};
+
+// ... or, for float fields, a key that orders the cells the way the
+// simulated order of Sec. 3.3 (footnote) orders the vertices, with no ties:
+// the value widened exactly to double (-0 becomes +0 first, as IEEE equality
+// treats them alike), its 29 unused low mantissa bits carrying the cell's
+// position in the staged box.  Cells are numbered in the order of their
+// global indices, so between equal values the later cell wins; for negative
+// values a larger magnitude is a smaller value, so the position is stored
+// reversed there.  Distinct floats stay ordered (they differ by at least
+// 2^29 units of the double's last place), and every pair of keys differs, so
+// one double max / min or one subtraction decides an SoS comparison.  The
+// outside value (a quiet NaN) stays a quiet NaN.
+struct TagKey {
+  static __device__ __forceinline__ double conv(float v, uint32_t cell) {
+    const double d = (double)(v + 0.0f);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    const uint32_t neg = (uint32_t)((long long)b >> 63);
+    return __longlong_as_double((long long)(b | ((cell ^ neg) & 0xFFFFu)));
+  }
+  // staged-box position of a key
+  static __device__ __forceinline__ uint32_t cell(double k) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(k);
+    const uint32_t neg = (uint32_t)((long long)b >> 63);
+    return ((uint32_t)b ^ neg) & 0xFFFFu;
+  }
+};
+
+template <int TY, int TZ, class V, class Conv = AsIs, class O = V>
+__device__ __forceinline__ void stage_rows(const FieldDev &fd, const V *__restrict__ src, O *S,
                                            BoxOrigin o) {
   using B = Box<TY, TZ>;
   constexpr int NR = B::H * B::D;             // rows of the halo box
@@ -90,12 +121,14 @@ __device__ __forceinline__ void stage_rows(const FieldDev &fd, const V *__restri
 #pragma unroll
   for (int k = 0; k < RPW; ++k) {
     const int row = w + k * TY;
-    if (row < NR) S[row * B::W + lane] = r[k];
+    const uint32_t c = (uint32_t)(row * B::W + lane);
+    if (row < NR) S[c] = Conv::conv(r[k], c);
   }
 #pragma unroll
   for (int k = 0; k < NEDGE; ++k) {
     const int t = tid + k * 64 * TY;
-    if (t < 2 * NR) S[(t >> 1) * B::W + 64 + (t & 1)] = e[k];
+    const uint32_t c = (uint32_t)((t >> 1) * B::W + 64 + (t & 1));
+    if (t < 2 * NR) S[c] = Conv::conv(e[k], c);
   }
 }
 
@@ -211,20 +244,85 @@ __device__ __forceinline__ void post_targets(const FieldDev &fd, const int32_t *
   }
 }
 
-// LDS of one check work-group: the staged box, the reference codes of its
-// own vertices (code byte | lower mask << 8), the link connectivity bits and
-// the field's slot offsets.  With both tables in LDS the vertex loop issues
-// no global load (a per-lane index into the descriptor would be one), so no
-// wait in it waits for the successor gathers still in flight: a wait for a
-// vector memory load also waits for every older load and store.
+// LDS of one check work-group: the staged box (float fields as tie-free
+// keys, double fields as values), the reference codes of its own vertices
+// (code byte | lower mask << 8), the link connectivity bits, the field's
+// slot offsets and, for the keyed boxes, the slot of every cell offset a
+// neighbour can have (offset + SLOT_BIAS; other entries unused).  With the
+// tables in LDS the vertex loop issues no global load.
 constexpr int CONN_WORDS = 512;  // one bit per 14-bit slot mask
+template <int TY, int TZ>
+struct CellSlots {
+  static constexpr int B = Box<TY, TZ>::PLANE + Box<TY, TZ>::W + 1;  // SLOT_BIAS
+  static constexpr int N = 2 * B + 1;
+};
 template <class T, int TY, int TZ>
 struct CheckLds {
-  T S[Box<TY, TZ>::NE];
-  uint32_t ref[TZ][64 * TY];
+  double S[Box<TY, TZ>::NE];
+  uint32_t ref[sizeof(T) == 4 ? 1 : TZ][64 * TY];  // keyed boxes keep the codes in registers
   uint32_t conn[CONN_WORDS];
   int32_t dlt[16];
+  uint8_t slot_of[CellSlots<TY, TZ>::N];
 };
+
+// Maximum / minimum of two keys with v_max_f64 / v_min_f64 as they are: a
+// quiet NaN operand yields the other one.  (fmax would first quiet each
+// operand with a separate instruction, since a value loaded from memory
+// could be a signalling NaN; staged keys never are.)
+__device__ __forceinline__ double key_max(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double key_min(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// check_vertex on tie-free keys (float fields, see TagKey): one double
+// max / min each over the closed neighbourhood gives the steepest ascent /
+// descent, whose slots come from their cells through L.slot_of; the lower
+// mask is the sign of key(neighbour) - key(i), one subtraction and one
+// funnel shift per slot.  Same requests as check_vertex.
+// closed_order on tie-free keys: P points at the key of the vertex (cell cc
+// of the staged box), vm is its mask of in-domain slots.
+template <int TY, int TZ>
+__device__ __forceinline__ void key_order(const double *P, uint32_t cc, const uint8_t *slot_of,
+                                          uint32_t vm, int &asc, int &desc, uint32_t &lower) {
+  using B = Box<TY, TZ>;
+  double v[NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) v[s] = P[DZS[s] * B::PLANE + DYS[s] * B::W + DXS[s]];
+  const double c = P[0];
+  double hi = c, lo = c;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    hi = key_max(hi, v[s]);  // a quiet NaN (outside the domain) is ignored
+    lo = key_min(lo, v[s]);
+  }
+  lower = 0;
+#pragma unroll
+  for (int s = NSLOT - 1; s >= 0; --s) {
+    const double d = v[s] - c;  // never zero: keys are distinct
+    const uint32_t dh = (uint32_t)((unsigned long long)__double_as_longlong(d) >> 32);
+    lower = __builtin_amdgcn_alignbit(lower, dh, 31);  // lower << 1 | sign(d)
+  }
+  lower &= vm;
+  asc = slot_of[TagKey::cell(hi) - cc + CellSlots<TY, TZ>::B];
+  desc = slot_of[TagKey::cell(lo) - cc + CellSlots<TY, TZ>::B];
+}
+
+// Fills the cell-offset -> slot table of a keyed box (threads 0..14).
+template <int TY, int TZ>
+__device__ __forceinline__ void fill_slot_of(uint8_t *slot_of, int tid) {
+  using B = Box<TY, TZ>;
+  if (tid < NSLOT + 1) {
+    const int s = tid;
+    const int off = s == SELF ? 0 : DZS[s] * B::PLANE + DYS[s] * B::W + DXS[s];
+    slot_of[off + CellSlots<TY, TZ>::B] = (uint8_t)s;
+  }
+}
 
 // Copies the connectivity bits into LDS; the barrier of the first box
 // orders it before any use.
@@ -241,12 +339,14 @@ __device__ __forceinline__ bool one_component(const uint32_t *conn, uint32_t m) 
   return (conn[m >> 5] >> (m & 31u)) & 1u;
 }
 
-// LDS of one reference-topology work-group: the staged box of f and the
-// link connectivity bits.
+// LDS of one reference-topology work-group: the staged box of f (keys for
+// float fields, values for double fields), the link connectivity bits and
+// the cell-offset -> slot table.
 template <class T, int TY, int TZ>
 struct RefLds {
-  T S[Box<TY, TZ>::NE];
+  double S[Box<TY, TZ>::NE];
   uint32_t conn[CONN_WORDS];
+  uint8_t slot_of[CellSlots<TY, TZ>::N];
 };
 
 // Reference topology of f on one box (Sec. 3.1-3.2): per vertex the code
@@ -262,7 +362,13 @@ __device__ __forceinline__ void ref_box(const FieldDev &fd, BoxOrigin o, RefLds<
   const bool col = x < fd.nx && y < fd.ny;
   const uint32_t plane = (uint32_t)fd.nx * (uint32_t)fd.ny;
   const uint32_t i0 = (uint32_t)x + (uint32_t)fd.nx * ((uint32_t)y + (uint32_t)fd.ny * (uint32_t)o.z0);
-  stage_rows<TY, TZ>(fd, (const T *)fd.f, L.S, o);
+  constexpr bool keyed = sizeof(T) == 4;
+  if (keyed) {
+    fill_slot_of<TY, TZ>(L.slot_of, ly * 64 + lx);
+    stage_rows<TY, TZ, float, TagKey, double>(fd, (const float *)fd.f, L.S, o);
+  } else {
+    stage_rows<TY, TZ, double, AsIs, double>(fd, (const double *)fd.f, L.S, o);
+  }
   const bool interior = o.x0 >= 1 && o.x0 + 64 <= fd.nx - 1 && o.y0 >= 1 &&
                         o.y0 + TY <= fd.ny - 1 && o.z0 >= 1 && o.z0 + TZ <= fd.nz - 1;
   __syncthreads();
@@ -271,11 +377,15 @@ __device__ __forceinline__ void ref_box(const FieldDev &fd, BoxOrigin o, RefLds<
     const int z = o.z0 + k;
     if (col && z < fd.nz) {
       const uint32_t i = i0 + k * plane;
-      const T *c = L.S + (k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1;
+      const uint32_t cc = (uint32_t)((k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1);
+      const double *c = L.S + cc;
       const uint32_t vm = interior ? 0x3FFFu : slots_in_domain(x, y, z, fd.nx, fd.ny, fd.nz);
       int asc, desc;
       uint32_t lower;
-      closed_order<T>(c, -B::PLANE, B::PLANE, asc, desc, lower);
+      if (keyed)
+        key_order<TY, TZ>(c, cc, L.slot_of, vm, asc, desc, lower);
+      else
+        closed_order<double>(c, -B::PLANE, B::PLANE, asc, desc, lower);
       uint32_t low = lower;
       if (lower != 0 && lower != vm &&
           !(one_component(L.conn, lower) && one_component(L.conn, vm & ~lower)))
@@ -286,57 +396,149 @@ __device__ __forceinline__ void ref_box(const FieldDev &fd, BoxOrigin o, RefLds<
   }
 }
 
-// CheckConstraints on one box: stage g (and the box's reference codes), add
-// the targets every vertex names to the target set (and, in original mode,
-// write g's descent / ascent pointers).  With the reformulated event
-// constraints (Sec. 4.3) every critical point of f is also compared with the
-// next critical point in f's order: when g inverts the pair, the lower one
-// (this vertex) goes down.  The successor's value is gathered from g while
-// the box is checked.  The caller synchronises the block after it.
-template <class T, int TY, int TZ>
-__device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, CheckLds<T, TY, TZ> &L) {
+// Requests of a vertex (as check_vertex) once its steepest slots in g and
+// its lower mask in g are known.
+__device__ __forceinline__ uint32_t requests_of(const uint32_t *conn, uint32_t vm, int asc, int desc,
+                                                uint32_t lower, uint32_t codeb, uint32_t lowf) {
+  const int asc_f = (int)(codeb & 15u), desc_f = (int)(codeb >> 4);
+  const uint32_t lower_f = lowf & LOW_MASK;
+  bool link_rule = (lowf & LOW_SADDLE) != 0;
+  if (!link_rule && lower != lower_f && asc_f != SELF && desc_f != SELF && lower != 0 &&
+      lower != vm) {
+    const uint32_t up = vm & ~lower;
+    const bool regular_g = ((conn[lower >> 5] >> (lower & 31u)) & 1u) &&
+                           ((conn[up >> 5] >> (up & 31u)) & 1u);
+    link_rule = !regular_g;
+  }
+  uint32_t req = 0;
+  if (asc != asc_f) req |= 1u << asc;
+  if (desc != desc_f) req |= 1u << desc_f;
+  if (link_rule) {
+    const uint32_t diff = lower ^ lower_f;
+    req |= diff & lower_f;
+    if (diff & ~lower_f) req |= 1u << SELF;
+  }
+  return req;
+}
+
+// Keys of one plane of a thread's column walk: the vertex's cell and its six
+// in-plane neighbours (slots 0..5), read from the staged box.
+struct PlaneKeys {
+  double c, xp, xm, yp, ym, xyp, xym;
+};
+
+// The keyed check of the TZ vertices of one (x, y) column of a box, walked
+// upwards in z.  A vertex's closed neighbourhood is the 2 x 2 square of cells
+// at and above-right of it in its own plane and the plane above, plus the
+// square at and below-left of it in its own plane and the plane below (the
+// two cubes of the Freudenthal star).  Walking up, each plane's cells are
+// read once (7 reads per vertex instead of 15) and the maxima / minima of
+// the squares are kept, so the steepest neighbours cost 9 max and 9 min
+// operations per vertex.  Requests and, in original mode, g's pointers are
+// those of check_vertex.
+template <int TY, int TZ>
+__device__ __forceinline__ void check_column_keys(const FieldDev &fd, CheckLds<float, TY, TZ> &L,
+                                                  BoxOrigin o, const uint32_t *refs, bool interior) {
+  using B = Box<TY, TZ>;
+  constexpr int W = B::W;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int x = o.x0 + lx, y = o.y0 + ly;
+  const bool col = x < fd.nx && y < fd.ny;
+  const uint32_t plane = (uint32_t)fd.nx * (uint32_t)fd.ny;
+  const uint32_t i0 = (uint32_t)x + (uint32_t)fd.nx * ((uint32_t)y + (uint32_t)fd.ny * (uint32_t)o.z0);
+  const uint32_t cell0 = (uint32_t)((ly + 1) * W + lx + 1);  // this column's cell in plane 0
+  const double *S = L.S;
+  // plane 0 (below the box): the lower-left square; plane 1: the upper-right square
+  double m_c = S[cell0], m_xm = S[cell0 - 1], m_ym = S[cell0 - W], m_xym = S[cell0 - W - 1];
+  double m_max = key_max(key_max(m_c, m_xm), key_max(m_ym, m_xym));
+  double m_min = key_min(key_min(m_c, m_xm), key_min(m_ym, m_xym));
+  PlaneKeys c;
+  {
+    const uint32_t b = cell0 + B::PLANE;
+    c.c = S[b];
+    c.xp = S[b + 1];
+    c.yp = S[b + W];
+    c.xyp = S[b + W + 1];
+  }
+  double cp_max = key_max(key_max(c.c, c.xp), key_max(c.yp, c.xyp));
+  double cp_min = key_min(key_min(c.c, c.xp), key_min(c.yp, c.xyp));
+#pragma unroll
+  for (int k = 0; k < TZ; ++k) {
+    // this vertex's plane (k + 1): the lower-left cells; the plane above: the
+    // upper-right square
+    const uint32_t b = cell0 + (uint32_t)(k + 1) * B::PLANE, bu = b + B::PLANE;
+    c.xm = S[b - 1];
+    c.ym = S[b - W];
+    c.xym = S[b - W - 1];
+    const double u_c = S[bu], u_xp = S[bu + 1], u_yp = S[bu + W], u_xyp = S[bu + W + 1];
+    const double cm_max = key_max(key_max(c.c, c.xm), key_max(c.ym, c.xym));
+    const double cm_min = key_min(key_min(c.c, c.xm), key_min(c.ym, c.xym));
+    const double up_max = key_max(key_max(u_c, u_xp), key_max(u_yp, u_xyp));
+    const double up_min = key_min(key_min(u_c, u_xp), key_min(u_yp, u_xyp));
+    const double hi = key_max(key_max(m_max, cm_max), key_max(cp_max, up_max));
+    const double lo = key_min(key_min(m_min, cm_min), key_min(cp_min, up_min));
+    const int z = o.z0 + k;
+    const uint32_t vm = interior ? 0x3FFFu : slots_in_domain(x, y, z, fd.nx, fd.ny, fd.nz);
+    // lower mask, slot 13 first so that slot s ends at bit s
+    const double nb[NSLOT] = {c.xp, c.xm, c.yp, c.ym, c.xyp, c.xym, u_c,
+                              m_c, u_xp, m_xm, u_yp, m_ym, u_xyp, m_xym};
+    uint32_t lower = 0;
+#pragma unroll
+    for (int s = NSLOT - 1; s >= 0; --s) {
+      const double d = nb[s] - c.c;  // never zero: keys are distinct
+      const uint32_t dh = (uint32_t)((unsigned long long)__double_as_longlong(d) >> 32);
+      lower = __builtin_amdgcn_alignbit(lower, dh, 31);
+    }
+    lower &= vm;
+    const uint32_t cc = b;
+    const int asc = L.slot_of[TagKey::cell(hi) - cc + CellSlots<TY, TZ>::B];
+    const int desc = L.slot_of[TagKey::cell(lo) - cc + CellSlots<TY, TZ>::B];
+    if (col && z < fd.nz) {
+      const uint32_t i = i0 + (uint32_t)k * plane;
+      const uint32_t r = requests_of(L.conn, vm, asc, desc, lower, refs[k] & 255u, refs[k] >> 8);
+      if (r) post_targets(fd, L.dlt, i, r);
+      if (fd.mode == 1) {  // original event constraints trace g's integral paths
+        glob(fd.lab)[i] = (uint32_t)((int)i + L.dlt[desc]);
+        glob(fd.lab)[fd.n + i] = (uint32_t)fd.n + (uint32_t)((int)i + L.dlt[asc]);
+      }
+    }
+    // move up one plane
+    m_c = c.c;
+    m_xm = c.xm;
+    m_ym = c.ym;
+    m_xym = c.xym;
+    m_max = cm_max;
+    m_min = cm_min;
+    c.c = u_c;
+    c.xp = u_xp;
+    c.yp = u_yp;
+    c.xyp = u_xyp;
+    cp_max = up_max;
+    cp_min = up_min;
+  }
+}
+
+// The plain (double field) check of one box's columns, vertex by vertex.
+template <int TY, int TZ>
+__device__ __forceinline__ void check_column_plain(const FieldDev &fd, CheckLds<double, TY, TZ> &L,
+                                                   BoxOrigin o, bool interior) {
   using B = Box<TY, TZ>;
   const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx;
   const int x = o.x0 + lx, y = o.y0 + ly;
   const bool col = x < fd.nx && y < fd.ny;
   const uint32_t plane = (uint32_t)fd.nx * (uint32_t)fd.ny;
   const uint32_t i0 = (uint32_t)x + (uint32_t)fd.nx * ((uint32_t)y + (uint32_t)fd.ny * (uint32_t)o.z0);
-  const bool pairs = fd.mode != 1;  // reformulated event constraints
-  uint32_t refs[TZ], sc[TZ];
-#pragma unroll
-  for (int k = 0; k < TZ; ++k) {  // issued with the staging loads, unconditionally
-    const bool in = col && o.z0 + k < fd.nz;
-    const uint32_t idx = in ? i0 + k * plane : 0u;
-    const uint32_t cb = glob(fd.code)[idx], lb = glob(fd.low)[idx];
-    refs[k] = cb | (lb << 8);
-    sc[k] = pairs && in ? glob(fd.succ)[idx] : NONE;
-  }
-  if (tid == 0) {  // constant indices: scalar loads, ordered by the barrier below
-#pragma unroll
-    for (int q = 0; q < 16; ++q) L.dlt[q] = fd.dlt[q];
-  }
-  stage_rows<TY, TZ>(fd, (const T *)fd.g, L.S, o);
-  // successor values, in flight during the check, from the compact array of
-  // critical-point values (small enough to stay in the memory-side cache)
-  T gs[TZ];
-#pragma unroll
-  for (int k = 0; k < TZ; ++k)
-    gs[k] = sc[k] != NONE ? glob((const T *)fd.cpv)[sc[k] & SUCC_SLOT] : T(0);
-#pragma unroll
-  for (int k = 0; k < TZ; ++k) L.ref[k][tid] = refs[k];
-  const bool interior = o.x0 >= 1 && o.x0 + 64 <= fd.nx - 1 && o.y0 >= 1 &&
-                        o.y0 + TY <= fd.ny - 1 && o.z0 >= 1 && o.z0 + TZ <= fd.nz - 1;
-  __syncthreads();
 #pragma unroll 1
   for (int k = 0; k < TZ; ++k) {
     const int z = o.z0 + k;
     if (col && z < fd.nz) {
       const uint32_t i = i0 + k * plane;
-      const T *c = L.S + (k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1;
+      const uint32_t cc = (uint32_t)((k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1);
+      const double *c = L.S + cc;
       const uint32_t rf = L.ref[k][tid];
       uint32_t av = 0, dv = 0;
-      const uint32_t r = check_vertex<T>(fd, L.conn, L.dlt, c, -B::PLANE, B::PLANE, x, y, z, i,
-                                         rf & 255u, rf >> 8, av, dv, interior);
+      const uint32_t r = check_vertex<double>(fd, L.conn, L.dlt, c, -B::PLANE, B::PLANE, x, y, z, i,
+                                              rf & 255u, rf >> 8, av, dv, interior);
       if (r) post_targets(fd, L.dlt, i, r);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
         glob(fd.lab)[i] = dv;
@@ -344,13 +546,46 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, Check
       }
     }
   }
+}
+
+// CheckConstraints on one box (Sec. 4.2): stage g (and the box's reference
+// codes), add the targets every vertex names to the target set (and, in
+// original mode, write g's descent / ascent pointers).  The order of the
+// critical points of f (Sec. 4.3) is tested by its own pass (order_quad).
+// The caller synchronises the block after it.
+template <class T, int TY, int TZ>
+__device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, CheckLds<T, TY, TZ> &L) {
+  constexpr bool keyed = sizeof(T) == 4;  // float fields: tie-free keys
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx;
+  const int x = o.x0 + lx, y = o.y0 + ly;
+  const bool col = x < fd.nx && y < fd.ny;
+  const uint32_t plane = (uint32_t)fd.nx * (uint32_t)fd.ny;
+  const uint32_t i0 = (uint32_t)x + (uint32_t)fd.nx * ((uint32_t)y + (uint32_t)fd.ny * (uint32_t)o.z0);
+  uint32_t refs[TZ];
 #pragma unroll
-  for (int k = 0; k < TZ; ++k) {
-    if (sc[k] == NONE) continue;
-    const T a = L.S[(k + 1) * B::PLANE + (ly + 1) * B::W + lx + 1];
-    // the successor is below in the simulated order: a lower value, or an
-    // equal one at a lower vertex index
-    if (gs[k] < a || (gs[k] == a && (sc[k] & SUCC_BELOW))) mark_target(fd.tmark, i0 + k * plane);
+  for (int k = 0; k < TZ; ++k) {  // issued with the staging loads, unconditionally
+    const bool in = col && o.z0 + k < fd.nz;
+    const uint32_t idx = in ? i0 + k * plane : 0u;
+    const uint32_t cb = glob(fd.code)[idx], lb = glob(fd.low)[idx];
+    refs[k] = cb | (lb << 8);
+  }
+  if (tid == 0) {  // constant indices: scalar loads, ordered by the barrier below
+#pragma unroll
+    for (int q = 0; q < 16; ++q) L.dlt[q] = fd.dlt[q];
+  }
+  if (keyed) fill_slot_of<TY, TZ>(L.slot_of, tid);
+  const bool interior = o.x0 >= 1 && o.x0 + 64 <= fd.nx - 1 && o.y0 >= 1 &&
+                        o.y0 + TY <= fd.ny - 1 && o.z0 >= 1 && o.z0 + TZ <= fd.nz - 1;
+  if constexpr (keyed) {
+    stage_rows<TY, TZ, float, TagKey, double>(fd, (const float *)fd.g, L.S, o);
+    __syncthreads();
+    check_column_keys<TY, TZ>(fd, L, o, refs, interior);
+  } else {
+    stage_rows<TY, TZ, double, AsIs, double>(fd, (const double *)fd.g, L.S, o);
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) L.ref[k][tid] = refs[k];
+    __syncthreads();
+    check_column_plain<TY, TZ>(fd, L, o, interior);
   }
 }
 
@@ -383,6 +618,40 @@ template <> struct Vec4<double> {
     glob(reinterpret_cast<f64x2 *>(p))[1] = b;
   }
 };
+
+// Reformulated event constraints (Sec. 4.3) on the ranks r .. r+3 of the
+// critical points in f's order: for each pair (r', r' + 1) with r' + 1 < K,
+// when g puts the one of rank r' + 1 below the one of rank r', the latter
+// (the lower one in f) goes down.  The values come from cpr, which apply
+// keeps current in f's order, so a pass streams it (one vector load per
+// lane; the value after the lane's four comes from the next lane when that
+// lane holds the next four, else from one more load).  Ties in g are broken
+// by the vertex index: cp_below holds, per rank, whether the next critical
+// point's index is the lower one.  Every lane of the wave calls this (the
+// shuffle); lanes with r >= K test nothing.  K may cut the ranks short of
+// the field's count (a batched item stops there).
+template <class T>
+__device__ __forceinline__ void order_quad(const FieldDev &fd, uint32_t r, uint32_t K,
+                                           bool next_in_lane) {
+  const T *V = (const T *)fd.cpr;
+  T a[4];
+  if (r + 4 <= K) {
+    Vec4<T>::load(V + r, a);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = r + c < K ? glob(V)[r + c] : (T)0;
+  }
+  const uint32_t bw = r < K ? glob(fd.cp_below)[r >> 5] >> (r & 31u) : 0u;
+  T nx = __shfl_down(a[0], 1);
+  if (!next_in_lane && r + 4 < K) nx = glob(V)[r + 4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const T lo = a[c], hi = c < 3 ? a[c + 1] : nx;
+    const bool below = (bw >> c) & 1u;
+    if (r + c + 1 < K && (hi < lo || (hi == lo && below)))
+      mark_target(fd.tmark, glob(fd.cp_idx)[r + c]);
+  }
+}
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
@@ -425,24 +694,56 @@ __device__ __forceinline__ uint32_t quad_marks(const FieldDev &fd, uint32_t q) {
   return *glob(reinterpret_cast<const uint32_t *>(fd.tmark + 4u * q));
 }
 
-// Inputs of one quad v .. v+3 of apply: value, f, edit count and (frontier
-// passes) the box of the previous critical point of each vertex; with the
+// What apply fetches one quad ahead: the quad's marks and, with the
+// reformulated constraints, the critical-point bitmask word and prefix count
+// of its 64-vertex chunk (raw: decoded only once they are needed, so the
+// loads stay in flight while the current quad is edited).
+struct QuadHead {
+  uint32_t m;
+  unsigned long long bits;
+  uint32_t off;
+};
+
+__device__ __forceinline__ QuadHead quad_head(const FieldDev &fd, uint32_t q, uint32_t nq) {
+  QuadHead h = {0u, 0ull, 0u};
+  if (q < nq) {
+    h.m = quad_marks(fd, q);
+    if (fd.mode != 1) {  // a quad lies in one 64-vertex chunk of the bitmask
+      h.bits = glob(fd.cpbits)[q >> 4];
+      h.off = glob(fd.cpoff)[q >> 4];
+    }
+  }
+  return h;
+}
+
+// Inputs of one quad v .. v+3 of apply: value, f and edit count; with the
 // reformulated constraints also which of them are critical points of f
-// (bits 0..3) and the vertex-order slot of the first of those.
+// (bits 0..3) and, for the marked ones, their ranks in f's order.
 template <class T>
 struct QuadIn {
   T g[4], f[4];
-  uint32_t c[4], pb[4];
-  uint32_t cpm, vo0;
+  uint32_t c[4];
+  uint32_t cpm;
+  uint32_t rank[4];
 };
 
 // Loads the inputs of the quad at v whose mark bytes are m (m != 0): vector
 // loads when the whole quad is in the field and aligned, else one load per
-// vertex (unmarked ones read vertex v, which is valid).  flag: this apply
-// sets the box flags of the next frontier pass.
+// vertex (unmarked ones read vertex v, which is valid).
 template <class T>
-__device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32_t m, bool flag,
+__device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, const QuadHead &h,
                                           QuadIn<T> &d) {
+  const uint32_t m = h.m;
+  d.cpm = 0;
+  if (fd.mode != 1) {  // ranks first: issued together with the value loads
+    const uint32_t sh = v & 63u;
+    d.cpm = (uint32_t)(h.bits >> sh) & 15u;
+    const uint32_t vo0 = h.off + (uint32_t)__popcll(h.bits & ((1ull << sh) - 1ull));
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (((d.cpm >> c) & 1u) && ((m >> (8 * c)) & 255u))
+        d.rank[c] = glob(fd.cp_rank)[vo0 + (uint32_t)__popc(d.cpm & ((1u << c) - 1u))];
+  }
   const T *G = (const T *)fd.g;
   const T *F = (const T *)fd.f;
   if (fd.vec && v + 3 < (uint32_t)fd.n) {
@@ -451,13 +752,6 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32
     const uint32_t c4 = *glob(reinterpret_cast<const uint32_t *>(fd.cnt + v));
 #pragma unroll
     for (int c = 0; c < 4; ++c) d.c[c] = (c4 >> (8 * c)) & 255u;
-    if (flag) {
-      const u32x4 p4 = *glob(reinterpret_cast<const u32x4 *>(fd.pred_box + v));
-      d.pb[0] = p4.x;
-      d.pb[1] = p4.y;
-      d.pb[2] = p4.z;
-      d.pb[3] = p4.w;
-    }
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -465,14 +759,7 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32
       d.g[c] = glob(G)[t];
       d.f[c] = glob(F)[t];
       d.c[c] = glob(fd.cnt)[t];
-      if (flag) d.pb[c] = glob(fd.pred_box)[t];
     }
-  }
-  if (fd.mode != 1) {  // a quad lies in one 64-vertex chunk of the bitmask
-    const uint32_t ch = v >> 6, sh = v & 63u;
-    const unsigned long long bits = glob(fd.cpbits)[ch];
-    d.cpm = (uint32_t)(bits >> sh) & 15u;
-    d.vo0 = glob(fd.cpoff)[ch] + (uint32_t)__popcll(bits & ((1ull << sh) - 1ull));
   }
 }
 
@@ -482,7 +769,7 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, uint32
 // and one 32-bit store of its counts (unmarked vertices keep theirs).
 // Returns the vertices whose value or count moved, as bits 0..3.
 template <class T>
-__device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, uint32_t m, bool flag,
+__device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, uint32_t m,
                                               const QuadIn<T> &d, EditCount &ec) {
   T *G = (T *)fd.g;
   const T xiT = (T)fd.xiT, delta = (T)fd.delta;
@@ -508,13 +795,9 @@ __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, ui
       nv = cand < L ? L : cand;
     }
     gn[c] = nv;
-    // the compact copy of critical-point values that the order test reads
-    if (fd.mode != 1 && ((d.cpm >> c) & 1u))
-      glob((T *)fd.cpv)[d.vo0 + (uint32_t)__popc(d.cpm & ((1u << c) - 1u))] = nv;
-    // the previous critical point in f's order compares itself with t
-    // (frontier passes run with the reformulated constraints, so cpm is set;
-    // pred_box is defined for critical points only)
-    if (flag && ((d.cpm >> c) & 1u) && d.pb[c] != NONE) glob(fd.bdirty)[d.pb[c]] = 1;
+    // a critical point of f: the copy of its value, in f's order, that the
+    // order pass streams
+    if ((d.cpm >> c) & 1u) glob((T *)fd.cpr)[d.rank[c]] = nv;
     moved |= 1u << c;
     ++ec.v[1];
     ec.v[3] += nv == L;
@@ -561,7 +844,8 @@ __device__ __forceinline__ void mark_moved_boxes(const FieldDev &fd, uint32_t v,
 }
 
 // ApplyBoundedEdits over quads q = q0, q0 + stride, ... (< nq): the marks
-// of the next quad are fetched before the current one is edited.  One quad
+// (and critical-point words) of the next quad are fetched before the current
+// one is edited.  One quad
 // per thread at a time keeps the register count, and so the number of waves
 // in flight, high.  Box flags for the next frontier pass are set unless the
 // last pass changed so many values that the next check covers every box
@@ -570,18 +854,17 @@ template <class T>
 __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uint32_t stride,
                                             uint32_t nq, EditCount &ec) {
   const bool flag = fd.frontier && !fd.st->noflag;
-  uint32_t m = q0 < nq ? quad_marks(fd, q0) : 0u;
+  QuadHead h = quad_head(fd, q0, nq);
   for (uint32_t q = q0; q < nq; q += stride) {
-    const uint32_t qn = q + stride;
-    const uint32_t mn = qn < nq ? quad_marks(fd, qn) : 0u;
+    const QuadHead hn = quad_head(fd, q + stride, nq);
     uint32_t moved = 0;
-    if (m) {
+    if (h.m) {
       QuadIn<T> d;
-      load_quad<T>(fd, 4u * q, m, flag, d);
-      moved = edit_quad<T>(fd, 4u * q, m, flag, d, ec);
+      load_quad<T>(fd, 4u * q, h, d);
+      moved = edit_quad<T>(fd, 4u * q, h.m, d, ec);
     }
     if (flag) mark_moved_boxes(fd, 4u * q, moved);
-    m = mn;
+    h = hn;
   }
 }
 
@@ -629,8 +912,8 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
   // Were the targets just applied named by a check that covered every box?
   if (ch == 0 && fd.frontier && !st->dense) {
     // A frontier pass skips boxes whose requests were all blocked, so it
-    // cannot tell a fixpoint from convergence (or count the residual): dense
-    // passes over the unchanged field settle it.
+    // cannot tell a fixpoint from convergence (or count the residual): a
+    // dense pass over the unchanged field settles it.
     st->dense = 1;
     st->noflag = 0;
   } else if (nt == 0) {

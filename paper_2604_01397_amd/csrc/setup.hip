@@ -77,7 +77,6 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd) {
     // descent (a lone vertex counts as a minimum)
     const uint32_t code = fd.code[i];
     cp = (code & 15u) == SELF || (code >> 4) == SELF || (fd.low[i] & LOW_SADDLE);
-    fd.succ[i] = NONE;
     if (fd.g != fd.g_hat) ((T *)fd.g)[i] = gi;
     if (!fd.resume) fd.cnt[i] = 0;
   }
@@ -228,7 +227,6 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_compact(FieldDev fd, void *k
   const T *F = (const T *)fd.f;
   const uint32_t vo = cp_order(fd.cpbits, fd.cpoff, i);
   fd.cp_vtx[vo] = i;
-  ((T *)fd.cpv)[vo] = ((const T *)fd.g)[i];
   using K = decltype(sort_key(T(0)));
   ((K *)keys_)[vo] = sort_key(F[i]);
 }
@@ -242,48 +240,38 @@ hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *, void *keys, hi
   return hipGetLastError();
 }
 
-// Check box (of the field's box shape) that holds vertex v.
-__device__ __forceinline__ uint32_t box_index(const FieldDev &fd, uint32_t v) {
-  const uint32_t x = v % (uint32_t)fd.nx, q = v / (uint32_t)fd.nx;
-  const uint32_t y = q % (uint32_t)fd.ny, z = q / (uint32_t)fd.ny;
-  return (x >> 6) + (uint32_t)fd.tiles_x * ((y >> fd.ty_shift) + (uint32_t)fd.tiles_y * (z >> fd.tz_shift));
-}
-
-// After the stable sort of the keys (payload = vertex-order slot): the
-// rank -> vertex map, each critical point's successor in f's order (its
-// slot, and whether its vertex index is the lower one: slots follow vertex
-// order) and, for frontier passes, each rank's box in box_r.
-__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint32_t *sorted_vo,
-                                                         uint32_t *box_r) {
+// After the stable sort of the keys (payload = vertex-order slot): per rank
+// in f's order the vertex and the current value (read in rank order, the
+// slot's vertex and value gathered), per slot its rank (a scattered store),
+// and per rank whether the next critical point has the lower vertex index
+// (slots follow vertex order, so the slots decide; one bit per rank, a word
+// per 32 ranks from a wave's ballot).
+template <class T>
+__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint32_t *sorted_vo) {
   const uint32_t r = blockIdx.x * SETUP_BLOCK + threadIdx.x;
   const uint32_t K = (uint32_t)fd.K;
-  if (r >= K) return;
-  const uint32_t vo = sorted_vo[r];
-  const uint32_t v = fd.cp_vtx[vo];
-  fd.cp_idx[r] = v;
-  if (r + 1 < K) {
-    const uint32_t so = sorted_vo[r + 1];
-    fd.succ[v] = so | (so < vo ? SUCC_BELOW : 0u);
-  } else {
-    fd.succ[v] = NONE;
+  bool below = false;
+  if (r < K) {
+    const uint32_t vo = sorted_vo[r];
+    const uint32_t v = fd.cp_vtx[vo];
+    fd.cp_idx[r] = v;
+    fd.cp_rank[vo] = r;
+    ((T *)fd.cpr)[r] = ((const T *)fd.g)[v];
+    below = r + 1 < K && sorted_vo[r + 1] < vo;
   }
-  if (fd.frontier) box_r[r] = box_index(fd, v);
+  const unsigned long long b = __ballot(below);
+  const uint32_t lane = threadIdx.x & 63u;
+  if (lane == 0 && r < K) fd.cp_below[r >> 5] = (uint32_t)b;
+  if (lane == 32 && r < K) fd.cp_below[r >> 5] = (uint32_t)(b >> 32);
 }
 
-// Frontier passes: every critical point learns the box of its predecessor
-// (read in rank order, so only the store is scattered).
-__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_pred(FieldDev fd, const uint32_t *box_r) {
-  const uint32_t r = blockIdx.x * SETUP_BLOCK + threadIdx.x;
-  if (r >= (uint32_t)fd.K) return;
-  fd.pred_box[fd.cp_idx[r]] = r > 0 ? box_r[r - 1] : NONE;
-}
-
-hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, uint32_t *box_r,
-                          hipStream_t s) {
+hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, hipStream_t s) {
   if (fd.K == 0) return hipSuccess;
   const int grid = (fd.K + SETUP_BLOCK - 1) / SETUP_BLOCK;
-  hipLaunchKernelGGL(k_cp_init, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo, box_r);
-  if (fd.frontier) hipLaunchKernelGGL(k_cp_pred, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, box_r);
+  if (fd.dtype == 0)
+    hipLaunchKernelGGL(k_cp_init<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
+  else
+    hipLaunchKernelGGL(k_cp_init<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
   return hipGetLastError();
 }
 
