@@ -288,6 +288,45 @@ def config4_specs(njobs: int = 1000, rate: float = 200.0, seed: int = 4,
              "seed": 4000 + j, "rel": 1e-3} for j in range(njobs)]
 
 
+def config4_source(edge: int = 1024, seed: int = 4) -> np.ndarray:
+    """The periodic volume the serving jobs are cut from: GRF k^-3, float32,
+    edge^3, synthesised on the host (so every job's input can be rebuilt on
+    the CPU bit for bit)."""
+    return grf3d(edge, seed, -3.0, dtype=np.float32)
+
+
+def config4_offsets(spec: dict, src_edge: int = 1024):
+    """(z, y, x) corner of job spec's block in the periodic source volume."""
+    return [int(v) for v in np.random.default_rng(spec["seed"]).integers(0, src_edge, 3)]
+
+
+def config4_job(source: np.ndarray, spec: dict) -> Case:
+    """Job spec's (L+2)^3 block (wrapping around the periodic source), its
+    eps = rel * range of the block and the uniform quantisation."""
+    e = spec["edge"]
+    n = source.shape[0]
+    idx = [(np.arange(e) + o) % n for o in config4_offsets(spec, n)]
+    f = np.ascontiguousarray(source[np.ix_(idx[0], idx[1], idx[2])])
+    eps = eps_for(f, spec["rel"])
+    return Case("job%04d_%d" % (spec["j"], e), f, quantize_uniform(f, eps), eps,
+                {"rel": spec["rel"], "quantizer": "uniform", "edge": e})
+
+
+def config4_job_device(source, spec: dict):
+    """config4_job() on a device copy of the source volume: the same block,
+    eps and quantisation bit for bit (exact min / max, the same rounding).
+    Returns (f, g_hat, eps)."""
+    import torch
+    e = spec["edge"]
+    n = source.shape[0]
+    off = config4_offsets(spec, n)
+    idx = [(torch.arange(e, device=source.device) + o) % n for o in off]
+    f = source.index_select(0, idx[0]).index_select(1, idx[1]).index_select(2, idx[2])
+    f = f.contiguous()
+    eps = eps_for_device(f, spec["rel"])
+    return f, quantize_uniform_device(f, eps), eps
+
+
 # ----------------------------------------------------------------------------
 # device-side generation for the serving workload (blocks appear in HBM, as
 # an in-situ simulation would leave them); same rules as the host versions
@@ -340,7 +379,9 @@ def quantize_uniform_device(f, eps: float):
 
     if f.dtype != torch.float32:
         raise TypeError("device quantiser handles float32 blocks")
-    b = 2.0 * eps
+    # the bin as a device tensor: torch divides by a Python scalar through its
+    # reciprocal, which can round differently from numpy's true division
+    b = torch.full((), 2.0 * eps, dtype=torch.float64, device=f.device)
     q = torch.round(f.double() / b) * b  # round half to even, as np.rint
     g = q.to(torch.float32)
     for _ in range(8):

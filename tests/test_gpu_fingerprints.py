@@ -1,0 +1,147 @@
+"""Oracle parity at the workloads' full sizes.
+
+tests/golden/make_fingerprints.py ran the CPU oracle once on every field of
+the 512^3 workload, the 96-field batch and the serving jobs with L <= 256,
+and stored SHA-256 fingerprints of the inputs, of g' and of the edit counts,
+with all counters.  Here the same inputs are rebuilt from the seeded
+generators, corrected on the GPU in the configurations the benchmark times
+(plain exz_correct with the default persistent frontier walk, the batched
+call, the serving loop) and compared: equal fingerprints mean equal arrays,
+bit for bit.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2604_01397_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+COUNTERS = ("iterations", "edited_vertices", "edit_ops", "lossless_vertices", "floor_vertices",
+            "residual_violations", "num_critical", "status")
+
+
+def _load(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail("missing fingerprint file %s (run tests/golden/make_fingerprints.py)" % name)
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _sha_host(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _sha_dev(t) -> str:
+    return _sha_host(t.contiguous().cpu().numpy())
+
+
+def _check(rec, g_out, cnt, res, label):
+    assert _sha_dev(g_out) == rec["g_out_sha256"], label
+    assert _sha_dev(cnt) == rec["cnt_sha256"], label
+    for k in COUNTERS:
+        assert res[k] == rec[k], (label, k, res[k], rec[k])
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = exactz.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.timeout(300)
+def test_c2_512cube_matches_oracle(ctx):
+    fp = _load("fingerprints_c2.json")["items"][0]
+    case = synth.config2(512)
+    print("c2: inputs", flush=True)
+    assert _sha_host(case.f) == fp["f_sha256"] and _sha_host(case.g_hat) == fp["g_hat_sha256"], \
+        "the generator's 512^3 input differs from the one the oracle corrected"
+    f = torch.from_numpy(case.f).cuda()
+    g = torch.from_numpy(case.g_hat).cuda()
+    del case
+    g_out, cnt, res = ctx.correct(f, g, fp["xi"])
+    torch.cuda.synchronize()
+    print("c2:", res, flush=True)
+    _check(fp, g_out, cnt, res, "c2")
+
+
+@pytest.mark.timeout(300)
+def test_c3_batched_and_plain_match_oracle(ctx):
+    fps = _load("fingerprints_c3.json")["items"]
+    specs = synth.config3_specs(96)
+    assert len(fps) == len(specs)
+    items = []
+    for spec, fp in zip(specs, fps):
+        c = synth.config3_field(spec)
+        assert c.name == fp["name"]
+        assert _sha_host(c.f) == fp["f_sha256"] and _sha_host(c.g_hat) == fp["g_hat_sha256"], c.name
+        items.append({"f": torch.from_numpy(c.f).cuda(), "g_hat": torch.from_numpy(c.g_hat).cuda(),
+                      "xi": c.xi})
+    print("c3: batched", flush=True)
+    out = ctx.correct_batch(items)
+    torch.cuda.synchronize()
+    for fp, (g_out, cnt, res) in zip(fps, out):
+        _check(fp, g_out, cnt, res, "batched " + fp["name"])
+    print("c3: plain", flush=True)
+    for fp, it in zip(fps, items):
+        g_out, cnt, res = ctx.correct(it["f"], it["g_hat"], it["xi"])
+        torch.cuda.synchronize()
+        _check(fp, g_out, cnt, res, "plain " + fp["name"])
+
+
+@pytest.mark.timeout(600)
+def test_c4_served_jobs_match_oracle():
+    """The serving jobs with L <= 256, run through the continuous-batching
+    server (inputs cut and quantised on the GPU from the uploaded source)."""
+    from paper_2604_01397_amd import exactz
+    from paper_2604_01397_amd.serve import DeviceExecutor, JobSpec, Server
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    data = _load("fingerprints_c4.json")
+    fps = {d["j"]: d for d in data["items"]}
+    print("c4: source volume", flush=True)
+    src = torch.from_numpy(synth.config4_source()).cuda()
+    specs = [s for s in synth.config4_specs(1000, 200.0) if s["j"] in fps]
+    assert len(specs) == len(fps)
+    jobs = []
+    for s in specs:
+        def make(stream, s=s):
+            f, g, eps = synth.config4_job_device(src, s)
+            fp = fps[s["j"]]
+            assert _sha_dev(f) == fp["f_sha256"] and _sha_dev(g) == fp["g_hat_sha256"], \
+                "job %d: the device-side input differs from the one the oracle corrected" % s["j"]
+            assert eps == fp["xi"], s["j"]
+            return f, g, eps
+        jobs.append(JobSpec(s["j"], 0.0, (s["edge"],) * 3, 4 * s["edge"] ** 3, make))
+    ctx = exactz.Context(0)
+    try:
+        ex = DeviceExecutor(ctx, keep_outputs=True)
+        free, _ = torch.cuda.mem_get_info()
+        rep = Server(ex, int(0.5 * free), max_active=32, iters_per_step=4,
+                     keep_outputs=True).run(jobs)
+        torch.cuda.synchronize()
+        print("c4:", rep.summary(), flush=True)
+        errors = ["job %d: %s" % (r.spec.job_id, r.error) for r in rep.records if r.error]
+        for r in rep.records:
+            if r.error:
+                continue
+            fp = fps[r.spec.job_id]
+            g_out, cnt = r.outputs
+            _check(fp, g_out, cnt, r.result | {"num_critical": fp["num_critical"]},
+                   "job %d" % r.spec.job_id)
+            r.outputs = None
+        assert not errors, errors
+        assert rep.summary()["completed"] == len(jobs)
+    finally:
+        ctx.close()
