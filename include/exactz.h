@@ -187,7 +187,7 @@ exz_status exz_correct_host(exz_ctx *ctx, const void *f, const void *g_hat, void
  * Same arguments, statuses and results as exz_correct (bit for bit), but the
  * call allocates nothing: its workspace is one static device buffer of
  * 128 MiB per GPU, held until the process ends, that every call on that GPU
- * shares.  A field whose workspace does not fit (about 6 bytes per vertex
+ * shares.  A field whose workspace does not fit (about 7 bytes per vertex
  * plus 32 (float32) or 44 (float64) bytes per critical point, path
  * workspace for the original mode or the certificate on top) returns
  * EXZ_E_NOMEM with a message; the per-vertex part is checked before any work

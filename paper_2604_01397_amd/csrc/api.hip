@@ -205,7 +205,7 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
   off[2] = L.add(8 * (size_t)fd.nchunk);                     // cpbits
   off[3] = L.add(4 * ((size_t)fd.nchunk + 1));               // cpoff
   off[4] = L.add(mark_bytes(fd));                            // target marks + zero padding
-  off[5] = 0;
+  off[5] = L.add(n);                                         // fe
   off[6] = own_cnt ? L.add(n) : 0;                           // cnt
   off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
   // dirty box flags, sized for the smallest box (64 x 1 x 1) so the
@@ -255,6 +255,7 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   fd.cpbits = (unsigned long long *)(base + oa[2]);
   fd.cpoff = (uint32_t *)(base + oa[3]);
   fd.tmark = (uint8_t *)(base + oa[4]);
+  fd.fe = (uint8_t *)(base + oa[5]);
   fd.bdirty = (uint8_t *)(base + oa[8]);
   fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
   fd.vec = quad_aligned(fd);

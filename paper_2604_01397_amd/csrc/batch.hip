@@ -570,6 +570,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.cpbits = (unsigned long long *)(b + oa[k][2]);
       fd.cpoff = (uint32_t *)(b + oa[k][3]);
       fd.tmark = (uint8_t *)(b + oa[k][4]);
+      fd.fe = (uint8_t *)(b + oa[k][5]);
       fd.bdirty = (uint8_t *)(b + oa[k][8]);
       uint8_t *cnt_io = fields[mem[k].index].cnt_io;
       fd.cnt = cnt_io ? cnt_io : (uint8_t *)(b + oa[k][6]);

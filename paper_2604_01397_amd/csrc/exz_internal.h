@@ -48,6 +48,8 @@ struct State {
   uint32_t nsaddle;       // saddles of f (original mode)
   int32_t dense;          // the next check covers every box (first pass, fixpoint confirmation)
   int32_t noflag;         // this iteration's apply sets no box flags (the next check is dense)
+  int32_t busy;           // the last apply changed many values (> n / 64): the next apply
+                          // fetches every quad's counts ahead
   uint32_t jump[MAX_JUMP_ROUNDS];  // pointer-jumping round flags
   int64_t iterations;
   int64_t edit_ops;
@@ -86,6 +88,8 @@ struct FieldDev {
   const void *g_hat;
   void *g;              // the field being corrected (g_out)
   uint8_t *cnt;
+  uint8_t *fe;          // n: the edit count at which the vertex's value reaches its lower
+                        // bound (the edits before it are plain steps of delta)
   uint8_t *code;
   uint16_t *low;
   unsigned long long *cpbits;

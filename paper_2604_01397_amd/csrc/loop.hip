@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(64) k_state_reset(State *st, int64_t max_iters
   st->nsaddle = 0;
   st->dense = 1;
   st->noflag = 1;  // the first iterations change values in nearly every box
+  st->busy = 1;
   st->iterations = st->edit_ops = st->lossless_total = st->floor_total = st->edited_total = 0;
   st->targets_total = 0;
   st->residual = 0;

@@ -698,19 +698,30 @@ __device__ __forceinline__ uint32_t quad_marks(const FieldDev &fd, uint32_t q) {
 // reformulated constraints, the critical-point bitmask word and prefix count
 // of its 64-vertex chunk (raw: decoded only once they are needed, so the
 // loads stay in flight while the current quad is edited).
+// When the last pass changed many values (busy), also the quad's edit counts
+// and final-edit counts (whole aligned quads only; ce = 0 otherwise), so
+// that the loads of f a final edit needs go out with the value loads.
 struct QuadHead {
   uint32_t m;
   unsigned long long bits;
   uint32_t off;
+  uint32_t c4, e4;
+  bool ce;
 };
 
-__device__ __forceinline__ QuadHead quad_head(const FieldDev &fd, uint32_t q, uint32_t nq) {
-  QuadHead h = {0u, 0ull, 0u};
+__device__ __forceinline__ QuadHead quad_head(const FieldDev &fd, uint32_t q, uint32_t nq,
+                                              bool busy) {
+  QuadHead h = {0u, 0ull, 0u, 0u, 0u, false};
   if (q < nq) {
     h.m = quad_marks(fd, q);
     if (fd.mode != 1) {  // a quad lies in one 64-vertex chunk of the bitmask
       h.bits = glob(fd.cpbits)[q >> 4];
       h.off = glob(fd.cpoff)[q >> 4];
+    }
+    if (busy && fd.vec && 4u * q + 3 < (uint32_t)fd.n) {
+      h.c4 = *glob(reinterpret_cast<const uint32_t *>(fd.cnt + 4u * q));
+      h.e4 = *glob(reinterpret_cast<const uint32_t *>(fd.fe + 4u * q));
+      h.ce = true;
     }
   }
   return h;
@@ -721,8 +732,9 @@ __device__ __forceinline__ QuadHead quad_head(const FieldDev &fd, uint32_t q, ui
 // (bits 0..3) and, for the marked ones, their ranks in f's order.
 template <class T>
 struct QuadIn {
-  T g[4], f[4];
-  uint32_t c[4];
+  T g[4];
+  uint32_t c[4], e[4];  // edit counts, and the counts at which each reaches its floor
+  T fl[4];              // f of the marked vertices whose next edit stores L
   uint32_t cpm;
   uint32_t rank[4];
 };
@@ -745,26 +757,41 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, const 
         d.rank[c] = glob(fd.cp_rank)[vo0 + (uint32_t)__popc(d.cpm & ((1u << c) - 1u))];
   }
   const T *G = (const T *)fd.g;
-  const T *F = (const T *)fd.f;
-  if (fd.vec && v + 3 < (uint32_t)fd.n) {
-    Vec4<T>::load(G + v, d.g);
-    Vec4<T>::load(F + v, d.f);
-    const uint32_t c4 = *glob(reinterpret_cast<const uint32_t *>(fd.cnt + v));
+  if (h.ce) {  // counts fetched ahead: f goes out with the values
 #pragma unroll
-    for (int c = 0; c < 4; ++c) d.c[c] = (c4 >> (8 * c)) & 255u;
+    for (int c = 0; c < 4; ++c) {
+      d.c[c] = (h.c4 >> (8 * c)) & 255u;
+      d.e[c] = (h.e4 >> (8 * c)) & 255u;
+    }
+    Vec4<T>::load(G + v, d.g);
+  } else if (fd.vec && v + 3 < (uint32_t)fd.n) {
+    Vec4<T>::load(G + v, d.g);
+    const uint32_t c4 = *glob(reinterpret_cast<const uint32_t *>(fd.cnt + v));
+    const uint32_t e4 = *glob(reinterpret_cast<const uint32_t *>(fd.fe + v));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      d.c[c] = (c4 >> (8 * c)) & 255u;
+      d.e[c] = (e4 >> (8 * c)) & 255u;
+    }
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const uint32_t t = ((m >> (8 * c)) & 255u) ? v + c : v;
       d.g[c] = glob(G)[t];
-      d.f[c] = glob(F)[t];
       d.c[c] = glob(fd.cnt)[t];
+      d.e[c] = glob(fd.fe)[t];
     }
   }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (((m >> (8 * c)) & 255u) && d.c[c] + 1 == d.e[c]) d.fl[c] = glob((const T *)fd.f)[v + c];
 }
 
 // ApplyBoundedEdits on the vertices v .. v+3 whose mark bytes in m are set,
 // from the inputs d; clears the marks and adds this thread's counts to ec.
+// A vertex's value is a plain step of delta below the last one until its
+// count reaches fe, where it becomes L (f is read for those edits only), and
+// blocked after that (its value is L).
 // A whole aligned quad is written back with one vector store of its values
 // and one 32-bit store of its counts (unmarked vertices keep theirs).
 // Returns the vertices whose value or count moved, as bits 0..3.
@@ -782,17 +809,16 @@ __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, ui
     cw |= d.c[c] << (8 * c);
     if (!((m >> (8 * c)) & 255u)) continue;
     ++ec.v[0];
-    const T L = lower_bound(d.f[c], xiT);
-    if (d.g[c] == L) continue;  // at the floor: blocked
+    if (d.c[c] >= d.e[c]) continue;  // at the floor: blocked
     const uint32_t cn = d.c[c] + 1;
-    cw = (cw & ~(255u << (8 * c))) | ((cn & 255u) << (8 * c));
+    cw = (cw & ~(255u << (8 * c))) | (cn << (8 * c));
     T nv;
-    if (cn > (uint32_t)fd.N) {
-      nv = L;  // (N+1)-th edit: store the lower bound itself
-      ++ec.v[2];
+    if (cn == d.e[c]) {
+      nv = lower_bound(d.fl[c], xiT);  // a clamped step or the (N+1)-th edit
+      ++ec.v[3];
+      ec.v[2] += cn > (uint32_t)fd.N;
     } else {
-      const T cand = d.g[c] - delta;
-      nv = cand < L ? L : cand;
+      nv = d.g[c] - delta;
     }
     gn[c] = nv;
     // a critical point of f: the copy of its value, in f's order, that the
@@ -800,7 +826,6 @@ __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, ui
     if ((d.cpm >> c) & 1u) glob((T *)fd.cpr)[d.rank[c]] = nv;
     moved |= 1u << c;
     ++ec.v[1];
-    ec.v[3] += nv == L;
     ec.v[4] += cn == 1;
   }
   if (moved) {
@@ -854,9 +879,10 @@ template <class T>
 __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uint32_t stride,
                                             uint32_t nq, EditCount &ec) {
   const bool flag = fd.frontier && !fd.st->noflag;
-  QuadHead h = quad_head(fd, q0, nq);
+  const bool busy = fd.st->busy != 0;
+  QuadHead h = quad_head(fd, q0, nq, busy);
   for (uint32_t q = q0; q < nq; q += stride) {
-    const QuadHead hn = quad_head(fd, q + stride, nq);
+    const QuadHead hn = quad_head(fd, q + stride, nq, busy);
     uint32_t moved = 0;
     if (h.m) {
       QuadIn<T> d;
@@ -927,6 +953,7 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
     // would be flagged, so the next apply skips the flags
     st->dense = st->noflag;
     st->noflag = fd.frontier && ch > NOFLAG_PER_BOX * (uint32_t)fd.ntiles;
+    st->busy = ch > (uint32_t)fd.n / 64;
     st->iterations += 1;
     st->edit_ops += ch;
     st->lossless_total += v[2];

@@ -67,11 +67,31 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd) {
     const T *F = (const T *)fd.f;
     const T *Gh = (const T *)fd.g_hat;
     const T fi = F[i], gi = Gh[i];
+    const T xiT = (T)fd.xiT;
+    const T L = lower_bound(fi, xiT);
     if (!isfinite(fi) || !isfinite(gi)) {
       atomicOr(&fd.st->err, ERR_NONFINITE);
     } else {
-      const T xiT = (T)fd.xiT;
-      if (gi < lower_bound(fi, xiT) || gi > upper_bound(fi, xiT)) atomicOr(&fd.st->err, ERR_BOUND);
+      if (gi < L || gi > upper_bound(fi, xiT)) atomicOr(&fd.st->err, ERR_BOUND);
+    }
+    // The edits of a vertex follow one fixed sequence (Sec. 3.3): steps of
+    // delta while they stay above L, then one edit that stores L (a clamped
+    // step, or the (N+1)-th edit), after which the vertex is blocked.  Its
+    // count at that edit is fixed by the value and count it starts from, so
+    // apply needs f (for L) only there.
+    {
+      const uint32_t c0 = fd.resume ? fd.cnt[i] : 0u;
+      const T delta = (T)fd.delta;
+      uint32_t e = c0;
+      if (!(gi == L)) {
+        T g = gi;
+        for (e = c0 + 1; e <= (uint32_t)fd.N; ++e) {
+          const T cand = g - delta;
+          if (cand < L || cand == L) break;
+          g = cand;
+        }
+      }
+      fd.fe[i] = (uint8_t)min(e, 255u);
     }
     // a maximum is its own steepest ascent, a minimum its own steepest
     // descent (a lone vertex counts as a minimum)

@@ -219,6 +219,25 @@ def test_float64_grf_bit_exact(ctx):
     _compare(ctx, c.f, c.g_hat, c.xi, c.name)
 
 
+def test_float64_grf128_bit_exact(ctx):
+    """float64 volume at 128^3 (the 8-byte path over the persistent box walk,
+    several boxes per work-group, frontier passes)."""
+    c = synth.case_grf3d(128, seed=13, slope=-11.0 / 3.0, rel=1e-4, dtype=np.float64,
+                         quantizer="lorenzo")
+    res, _ = _compare(ctx, c.f, c.g_hat, c.xi, c.name)
+    print("128^3 f64:", res, flush=True)
+
+
+@pytest.mark.parametrize("n_steps", [1, 3, 10, 14])
+def test_n_steps_bit_exact(ctx, n_steps):
+    """Step counts across the range the boundary accepts (Sec. 3.3: Delta =
+    xi_T / N, the (N+1)-th edit lossless)."""
+    c = synth.case_grf3d(40, seed=31, slope=-11.0 / 3.0, rel=1e-3, quantizer="lorenzo")
+    _compare(ctx, c.f, c.g_hat, c.xi, c.name, n_steps=n_steps)
+    d = synth.case_gauss2d(128, seed=32, rel=1e-3)
+    _compare(ctx, d.f, d.g_hat, d.xi, d.name, n_steps=n_steps)
+
+
 # ----------------------------------------------------------------------------
 # original event constraints (integral paths by pointer jumping) and the
 # extremum-graph certificate
@@ -300,6 +319,54 @@ def test_certificate(ctx):
     # without certify the field is left untested
     _, _, r = ctx.correct(f, g, c.xi)
     assert r["certified"] == -1
+
+
+def _terminus(info, v, key):
+    while info[v][key] != v:
+        v = info[v][key]
+    return v
+
+
+def _certificate_by_checker(cx, f, h):
+    """What the device certificate decides, from the brute-force link analysis
+    of oracle/checker.py: every vertex keeps its critical type (minimum,
+    maximum, saddle, regular) and the ends of its steepest-descent and
+    steepest-ascent paths."""
+    from oracle import checker
+    fi, gi = checker.classify(cx, f), checker.classify(cx, h)
+    for v in range(cx.n):
+        if fi[v]["type"] != gi[v]["type"]:
+            return 0
+        for key in ("desc", "asc"):
+            if _terminus(fi, v, key) != _terminus(gi, v, key):
+                return 0
+    return 1
+
+
+@pytest.mark.parametrize("shape,seed", [((23, 19), 51), ((7, 8, 9), 52), ((6, 5, 11), 53)])
+def test_certificate_matches_checker(ctx, shape, seed):
+    """The device certificate against the checker on the same g', after one,
+    two, three passes and at the fixpoint, in both event modes; where it
+    certifies, the extremum graphs (Sec. 4.1) are equal."""
+    from oracle import checker
+    from paper_2604_01397_amd import exactz
+    rng = np.random.default_rng(seed)
+    f, g, xi = _rand_case(rng, shape, np.float32, "normal")
+    cx = checker.Complex(list(shape))
+    seen = set()
+    for mode in (exactz.REFORMULATED, exactz.ORIGINAL):
+        for max_iters in (1, 2, 3, 0):
+            print("case: certificate", shape, "mode", mode, "max_iters", max_iters, flush=True)
+            g_out, _, r = ctx.correct(_dev(f), _dev(g), xi, mode=mode, max_iters=max_iters,
+                                      certify=True)
+            torch.cuda.synchronize()
+            h = g_out.cpu().numpy()
+            want = _certificate_by_checker(cx, f, h)
+            assert r["certified"] == want, (mode, max_iters, r)
+            if want:
+                assert checker.extremum_graph(cx, f) == checker.extremum_graph(cx, h)
+            seen.add(want)
+    assert seen == {0, 1}, "the cases should exercise both outcomes"
 
 
 # ----------------------------------------------------------------------------

@@ -61,8 +61,8 @@ def test_noalloc_rejects_fields_beyond_its_buffer():
         pytest.skip("no GPU")
     ctx = exactz.Context(0)
     try:
-        # 512 x 512 x 128 needs about 6 bytes per vertex of per-vertex
-        # workspace (200 MB): refused before any work is issued
+        # 512 x 512 x 128 needs about 7 bytes per vertex of per-vertex
+        # workspace (235 MB): refused before any work is issued
         f = torch.zeros((128, 512, 512), dtype=torch.float32, device="cuda")
         with pytest.raises(exactz.ExactzError) as e:
             ctx.correct_noalloc(f, f.clone(), 0.1)
