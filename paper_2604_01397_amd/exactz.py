@@ -71,6 +71,13 @@ def load(path: str | None = None):
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise ImportError("libexactz.so not built: run __graft_entry__.build() (expected %s)" % path)
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that one copy (loaded the other way
+    # round, the process holds two runtimes and only one of them sees the GPU)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.exz_ctx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(p)]

@@ -176,7 +176,8 @@ class DeviceExecutor:
     job's copy of g_hat.
     """
 
-    def __init__(self, ctx, n_steps: int = 5, keep_outputs: bool = False):
+    def __init__(self, ctx, n_steps: int = 5, keep_outputs: bool = False, tuned: bool = False,
+                 tune_cache: Optional[str] = None):
         import torch
 
         from . import exactz
@@ -187,6 +188,14 @@ class DeviceExecutor:
         self.keep = keep_outputs
         self.main = torch.cuda.Stream()
         self.side = torch.cuda.Stream()
+        # batched launch options from the autotune table's serving entry, set
+        # once before the first job (a job keeps the box shape it was created
+        # with, and the jobs of one step must share it)
+        self.tuned_options = None
+        if tuned:
+            from . import autotune
+            key = autotune.make_serving_key(autotune.device_arch(ctx.device))
+            self.tuned_options = autotune.apply_batch_options(ctx, key, tune_cache)
 
     def footprint(self, spec) -> int:
         shape_xyz = tuple(reversed(spec.shape))

@@ -44,3 +44,41 @@ def test_tune_then_correct(tmp_path):
         assert r["iterations"] == r2["iterations"]
     finally:
         tc.close()
+
+
+def test_tune_batch_then_correct_batch_matches_oracle(tmp_path):
+    """A batched tuning run (reduced axes) stores an entry; the tuned batch
+    corrects a mix of 1-D, 2-D and 3-D float32 / float64 fields exactly as
+    the oracle does."""
+    import oracle
+    from paper_2604_01397_amd import autotune, exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cache = str(tmp_path / "tune.json")
+    cases = [synth.case_grf3d(24, seed=61, rel=1e-3),
+             synth.case_grf3d((9, 17, 40), seed=62, rel=1e-3, dtype=np.float64),
+             synth.case_gauss2d(70, seed=63, rel=1e-3),
+             synth.case_gauss2d(33, seed=64, rel=1e-3, ny=1)]
+    items = [{"f": torch.from_numpy(c.f).cuda(), "g_hat": torch.from_numpy(c.g_hat).cuda(),
+              "xi": c.xi} for c in cases]
+    axes = {"btile3": [0, 804], "btile2": [0, 401], "bgrid_box": [0, 64], "bgrid_apply": [0, 64],
+            "bitem": [0, 1]}
+    ctx = exactz.Context(0)
+    try:
+        print("tuning a 4-field batch", flush=True)
+        entry = autotune.tune_batch(ctx, items, cache=cache, axes=axes, log=print)
+        assert entry["key"] == autotune.batch_key_of(items)
+        assert autotune.batch_options_for(entry["key"], cache) is not None
+    finally:
+        ctx.close()
+    tc = autotune.TunedContext(0, cache=cache)
+    try:
+        out = tc.correct_batch(items)
+        torch.cuda.synchronize()
+    finally:
+        tc.close()
+    for c, (g_out, cnt, res) in zip(cases, out):
+        ro, rc, st, _ = oracle.correct(c.f, c.g_hat, c.xi)
+        assert np.array_equal(g_out.cpu().numpy().view(np.uint8), ro.view(np.uint8)), c.name
+        assert np.array_equal(cnt.cpu().numpy(), rc), c.name
+        assert res["iterations"] == st["iterations"] and res["status"] == st["status"], c.name

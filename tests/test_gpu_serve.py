@@ -25,11 +25,18 @@ def _cases():
     ]
 
 
-def test_served_jobs_equal_alone_runs():
-    from paper_2604_01397_amd import exactz
+@pytest.mark.parametrize("tuned", [False, True])
+def test_served_jobs_equal_alone_runs(tuned, monkeypatch):
+    """With tuned=True the executor sets batched launch options per step from
+    the autotune table (here a table that answers every key with non-default
+    boxes, grid caps and item size)."""
+    from paper_2604_01397_amd import autotune, exactz
     from paper_2604_01397_amd.serve import DeviceExecutor, JobSpec, Server
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    if tuned:
+        monkeypatch.setattr(autotune, "batch_options_for", lambda key, cache=None: {
+            "btile3": 804, "btile2": 401, "bgrid_box": 64, "bgrid_apply": 64, "bitem": 1})
     cases = _cases()
     ctx = exactz.Context(0)
     try:
@@ -39,8 +46,10 @@ def test_served_jobs_equal_alone_runs():
                 f = torch.from_numpy(np.ascontiguousarray(c.f)).cuda()
                 g = torch.from_numpy(np.ascontiguousarray(c.g_hat)).cuda()
                 return f, g, c.xi
-            specs.append(JobSpec(j, 0.002 * j, c.f.shape, c.f.nbytes, make))
-        ex = DeviceExecutor(ctx, keep_outputs=True)
+            # all arrive at once, so that the budget (not the timing) decides how
+            # many run together
+            specs.append(JobSpec(j, 0.0, c.f.shape, c.f.nbytes, make))
+        ex = DeviceExecutor(ctx, keep_outputs=True, tuned=tuned)
         # a budget of about three jobs: later arrivals wait for memory
         budget = 3 * max(ex.footprint(s) for s in specs)
         print("serving", len(specs), "jobs, budget", budget, flush=True)
