@@ -156,8 +156,12 @@ exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value);
 
 /* Device workspace the library needs for one field, in bytes, beyond the
  * caller's f, g_hat, g_out and cnt_io.  Sizes the per-critical-point arrays
- * for the worst case (every vertex critical).  0 for invalid params. */
+ * for the worst case (every vertex critical).  0 for invalid params.
+ * exz_workspace_bytes_k: the same for a field with num_critical critical
+ * points (a count a job's result reports once its set-up has run; a
+ * scheduler may admit with an estimate and correct it then). */
 size_t exz_workspace_bytes(const exz_params *params);
+size_t exz_workspace_bytes_k(const exz_params *params, int64_t num_critical);
 
 /* Correct one field (Algorithm 1).
  *   f       device, n values of params->dtype, read-only
@@ -223,16 +227,37 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
 /* Serving primitives: a job keeps its correction state resident on the
  * device between calls, so a host scheduler can admit new jobs while others
  * iterate (continuous batching).  exz_job_create validates the field and
- * builds the reference topology of f (it allocates the job's workspace);
+ * builds the reference topology of f (it allocates the job's workspace; it
+ * waits for the validation, so a bad field is reported here);
  * exz_step advances every listed unfinished job by up to `iters` rounds in
- * shared batched launches; exz_job_poll reports completion; exz_job_release
- * frees the job's workspace (not the caller's buffers).  A job's final
- * state equals exz_correct on the same field. */
+ * shared batched launches; exz_job_poll reports completion (it waits for
+ * the work issued for the job); exz_job_release returns the job's workspace
+ * to the context (not the caller's buffers) once the device is done with
+ * it, without waiting.  A job's final state equals exz_correct on the same
+ * field (Algorithm 1 per field).
+ *
+ * For a scheduler that must never wait on the device:
+ *   exz_job_submit   as exz_job_create, but returns once the first half of
+ *                    the set-up (validation, reference topology, counts of
+ *                    critical points) is issued on `stream`; the second
+ *                    half (the critical points in f's order) is issued on
+ *                    the same stream by the first exz_step, exz_job_query or
+ *                    exz_job_poll that finds the first half ended, and a
+ *                    step skips the job until then.  `stream` must stay
+ *                    valid until then.  A validation error (EXZ_E_BOUND,
+ *                    EXZ_E_NONFINITE) is reported by exz_job_query /
+ *                    exz_job_poll with *done = 1; the job must still be
+ *                    released.
+ *   exz_job_query    as exz_job_poll, but never waits: *done and *result
+ *                    reflect the job's state after its latest step whose
+ *                    work has ended (*done = 0 while no step of it has). */
 typedef struct exz_job exz_job;
 exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, exz_job **out);
+exz_status exz_job_submit(exz_ctx *ctx, const exz_field *field, void *stream, exz_job **out);
 exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t iters,
                     void *stream);
 exz_status exz_job_poll(exz_job *job, int32_t *done, exz_result *result);
+exz_status exz_job_query(exz_job *job, int32_t *done, exz_result *result);
 exz_status exz_job_release(exz_job *job);
 size_t exz_job_bytes(const exz_params *params);
 

@@ -235,10 +235,9 @@ void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]) {
   off[11] = 0;
 }
 
-// Validation, reference topology, CP order (phases A and B).  On success fd
-// is ready for iterations and ctx->h_state holds the setup flags.
-exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_hat, void *g_out,
-                       uint8_t *cnt_io, int64_t max_iters, Arena &A, Arena &B, hipStream_t s) {
+exz_status setup_phase_a(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_hat,
+                         void *g_out, uint8_t *cnt_io, int64_t max_iters, Arena &A, hipStream_t s,
+                         State *h_state, uint32_t *h_k) {
   fd.f = f;
   fd.g_hat = g_hat;
   fd.g = g_out;
@@ -265,15 +264,13 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
   HIP_OR_FAIL(launch_setup(fd, ctx->d_conn, s));
   HIP_OR_FAIL(launch_scan_u32(fd.cpoff, fd.cpoff, (uint32_t)fd.nchunk, scan_tmp,
                               scan_tmp_words((uint32_t)fd.nchunk), s));
-  HIP_OR_FAIL(hipMemcpyAsync(ctx->h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
-  HIP_OR_FAIL(hipMemcpyAsync(ctx->h_k, fd.cpoff + fd.nchunk, sizeof(uint32_t),
-                             hipMemcpyDeviceToHost, s));
-  HIP_OR_FAIL(hipStreamSynchronize(s));
-  if (ctx->h_state->err & ERR_NONFINITE) return fail(ctx, EXZ_E_NONFINITE, "NaN or Inf in f or g_hat");
-  if (ctx->h_state->err & ERR_BOUND) return fail(ctx, EXZ_E_BOUND, "g_hat outside [f - xi, f + xi]");
-  const uint32_t K = *ctx->h_k;
-  fd.K = (int32_t)K;
+  HIP_OR_FAIL(hipMemcpyAsync(h_state, fd.st, sizeof(State), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipMemcpyAsync(h_k, fd.cpoff + fd.nchunk, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  return EXZ_OK;
+}
 
+exz_status setup_phase_b(exz_ctx *ctx, FieldDev &fd, uint32_t K, Arena &B, hipStream_t s) {
+  fd.K = (int32_t)K;
   Layout LB;
   size_t ob[12];
   layout_b(fd, K, LB, ob);
@@ -301,6 +298,19 @@ exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_
     HIP_OR_FAIL(launch_cp_init(fd, vals, s));
   }
   return EXZ_OK;
+}
+
+// Validation, reference topology, CP order (phases A and B).  On success fd
+// is ready for iterations and ctx->h_state holds the setup flags.
+exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_hat, void *g_out,
+                       uint8_t *cnt_io, int64_t max_iters, Arena &A, Arena &B, hipStream_t s) {
+  exz_status st = setup_phase_a(ctx, fd, f, g_hat, g_out, cnt_io, max_iters, A, s, ctx->h_state,
+                                ctx->h_k);
+  if (st != EXZ_OK) return st;
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  if (ctx->h_state->err & ERR_NONFINITE) return fail(ctx, EXZ_E_NONFINITE, "NaN or Inf in f or g_hat");
+  if (ctx->h_state->err & ERR_BOUND) return fail(ctx, EXZ_E_BOUND, "g_hat outside [f - xi, f + xi]");
+  return setup_phase_b(ctx, fd, *ctx->h_k, B, s);
 }
 
 // Path-tracing workspace: original event mode (g labels, f termini, saddle
@@ -404,6 +414,7 @@ exz_status exz_ctx_destroy(exz_ctx *ctx) {
   if (!ctx) return EXZ_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  free_graveyard(ctx);
   ctx->A.release();
   ctx->B.release();
   ctx->C.release();
@@ -485,18 +496,25 @@ exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value) {
   return EXZ_OK;
 }
 
-size_t exz_workspace_bytes(const exz_params *p) {
+size_t exz_workspace_bytes_k(const exz_params *p, int64_t num_critical) {
   FieldDev fd;
   if (prepare_field(nullptr, p, fd) != EXZ_OK) return 0;
+  if (num_critical < 0 || num_critical > fd.n) return 0;
   Layout LA, LB;
   size_t oa[9], ob[12];
   layout_a(fd, true, 0, p->event_mode == EXZ_EVENT_ORIGINAL || p->certify, LA, oa);
-  layout_b(fd, (uint32_t)fd.n, LB, ob);
+  layout_b(fd, (uint32_t)num_critical, LB, ob);
   Layout LC;
   size_t oc[6];
-  fd.K = fd.n;
+  fd.K = (int32_t)num_critical;
   layout_c(fd, p->event_mode == EXZ_EVENT_ORIGINAL, p->certify != 0, LC, oc);
   return LA.total + LB.total + LC.total;
+}
+
+size_t exz_workspace_bytes(const exz_params *p) {
+  FieldDev fd;
+  if (!p || prepare_field(nullptr, p, fd) != EXZ_OK) return 0;
+  return exz_workspace_bytes_k(p, fd.n);
 }
 
 static void fill_result(exz_result *r, const State &st, int status) {

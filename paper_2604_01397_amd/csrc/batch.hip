@@ -720,7 +720,81 @@ size_t exz_job_bytes(const exz_params *params) {
   return exz_workspace_bytes(params);
 }
 
-exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, exz_job **out) {
+}  // extern "C"
+
+namespace {
+
+bool event_ended(hipEvent_t e) { return !e || hipEventQuery(e) != hipErrorNotReady; }
+
+// Every event recorded for the job has completed: no device work of it is
+// left (a step's state copy follows that step's kernels).
+bool job_quiet(const exz_job *job) {
+  if (!event_ended(job->a_done) || !event_ended(job->ready)) return false;
+  for (int s = 0; s < exz_job::NSTATE; ++s)
+    if (job->recorded[s] && !event_ended(job->polled[s])) return false;
+  return true;
+}
+
+void free_job(exz_job *job) {
+  for (hipEvent_t e : {job->ready, job->a_done})
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : job->polled)
+    if (e) (void)hipEventDestroy(e);
+  job->A.release();
+  job->B.release();
+  if (job->pinned) (void)hipHostFree(job->pinned);
+  delete job;
+}
+
+// Frees the released jobs whose device work has ended.
+void reap(exz_ctx *ctx) {
+  auto &g = ctx->graveyard;
+  for (size_t k = 0; k < g.size();) {
+    if (job_quiet(g[k])) {
+      free_job(g[k]);
+      g[k] = g.back();
+      g.pop_back();
+    } else {
+      ++k;
+    }
+  }
+}
+
+// A submitted job whose phase A has ended: check the validation flags and
+// issue phase B on its creation stream (or mark the job failed).  Nothing
+// happens while phase A runs.
+exz_status job_advance(exz_job *job) {
+  if (job->phase != 0) return EXZ_OK;
+  const hipError_t q = hipEventQuery(job->a_done);
+  if (q == hipErrorNotReady) return EXZ_OK;
+  exz_ctx *ctx = job->ctx;
+  exz_status st = EXZ_OK;
+  const exz::State &hs = job->pinned->st[0];
+  if (q != hipSuccess) {
+    st = fail_b(ctx, EXZ_E_HIP, "job set-up failed on the device");
+  } else if (hs.err & ERR_NONFINITE) {
+    st = fail_b(ctx, EXZ_E_NONFINITE, "NaN or Inf in f or g_hat");
+  } else if (hs.err & ERR_BOUND) {
+    st = fail_b(ctx, EXZ_E_BOUND, "g_hat outside [f - xi, f + xi]");
+  } else {
+    st = setup_phase_b(ctx, job->fd, job->pinned->k, job->B, job->create_stream);
+    if (st == EXZ_OK && hipEventRecord(job->ready, job->create_stream) != hipSuccess)
+      st = fail_b(ctx, EXZ_E_HIP, "hipEventRecord failed");
+  }
+  if (st != EXZ_OK) {
+    job->phase = 2;
+    job->failed = st;
+    job->failed_msg = ctx->last_error;
+    return st;
+  }
+  job->result.num_critical = job->fd.K;
+  job->phase = 1;
+  return EXZ_OK;
+}
+
+// Phase A of a new job on `stream` (validation, reference topology, the
+// critical-point bitmask); *out gets a job in phase 0.
+exz_status job_begin(exz_ctx *ctx, const exz_field *field, void *stream, exz_job **out) {
   if (!ctx || !field || !out) return EXZ_E_INVALID;
   *out = nullptr;
   if (field->params.event_mode != EXZ_EVENT_REFORMULATED)
@@ -730,38 +804,79 @@ exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, ex
   if (field->params.resume && !field->cnt_io)
     return fail_b(ctx, EXZ_E_INVALID, "resume needs cnt_io");
   HIP_OR_FAIL_B(hipSetDevice(ctx->device));
+  reap(ctx);
   exz_job *job = new exz_job();
   job->ctx = ctx;
   job->A.budget = job->B.budget = &ctx->budget;  // the job's workspace counts against the budget
   job->params = field->params;
   std::memset(&job->result, 0, sizeof job->result);
   job->result.certified = -1;
-  exz_status st = prepare_field(ctx, &field->params, job->fd);
+  job->create_stream = (hipStream_t)stream;
+  job->last = (hipStream_t)stream;
+  job->phase = 0;
+  exz_status st = EXZ_OK;
+  if (hipHostMalloc((void **)&job->pinned, sizeof(exz_job::Pinned), hipHostMallocDefault) !=
+      hipSuccess) {
+    job->pinned = nullptr;
+    st = fail_b(ctx, EXZ_E_NOMEM, "hipHostMalloc failed");
+  }
+  std::vector<hipEvent_t *> evs = {&job->a_done, &job->ready};
+  for (hipEvent_t &e : job->polled) evs.push_back(&e);
+  for (hipEvent_t *e : evs) {
+    if (st == EXZ_OK && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+      *e = nullptr;
+      st = fail_b(ctx, EXZ_E_HIP, "hipEventCreateWithFlags failed");
+    }
+  }
+  if (st == EXZ_OK) st = prepare_field(ctx, &field->params, job->fd);
   if (st == EXZ_OK) {
     FieldDev &fd = job->fd;
     batch_geometry(batch_shape(ctx), fd);  // the boxes of the batched launches
-    st = setup_field(ctx, fd, field->f, field->g_hat, field->g_out, field->cnt_io,
-                     field->params.max_iters, job->A, job->B, (hipStream_t)stream);
+    st = setup_phase_a(ctx, fd, field->f, field->g_hat, field->g_out, field->cnt_io,
+                       field->params.max_iters, job->A, (hipStream_t)stream, &job->pinned->st[0],
+                       &job->pinned->k);
   }
-  // The set-up's last kernels (critical-point order) are still queued on
-  // `stream`: the first step that takes the job waits for this event.
-  if (st == EXZ_OK && hipEventCreateWithFlags(&job->ready, hipEventDisableTiming) != hipSuccess) {
-    job->ready = nullptr;
-    st = fail_b(ctx, EXZ_E_HIP, "hipEventCreateWithFlags failed");
-  }
-  if (st == EXZ_OK && hipEventRecord(job->ready, (hipStream_t)stream) != hipSuccess)
+  if (st == EXZ_OK && hipEventRecord(job->a_done, (hipStream_t)stream) != hipSuccess)
     st = fail_b(ctx, EXZ_E_HIP, "hipEventRecord failed");
   if (st != EXZ_OK) {
-    if (job->ready) (void)hipEventDestroy(job->ready);
-    job->A.release();
-    job->B.release();
-    delete job;
+    (void)hipStreamSynchronize((hipStream_t)stream);  // work issued before the failure
+    free_job(job);
     return st;
   }
-  job->result.num_critical = job->fd.K;
-  job->last = (hipStream_t)stream;
   *out = job;
   return EXZ_OK;
+}
+
+}  // namespace
+
+void free_graveyard(exz_ctx *ctx) {
+  for (exz_job *j : ctx->graveyard) free_job(j);
+  ctx->graveyard.clear();
+}
+
+extern "C" {
+
+exz_status exz_job_create(exz_ctx *ctx, const exz_field *field, void *stream, exz_job **out) {
+  exz_job *job = nullptr;
+  exz_status st = job_begin(ctx, field, stream, &job);
+  if (st != EXZ_OK) return st;
+  // wait for phase A: validation errors are returned here
+  if (hipEventSynchronize(job->a_done) != hipSuccess) {
+    free_job(job);
+    return fail_b(ctx, EXZ_E_HIP, "hipEventSynchronize failed");
+  }
+  st = job_advance(job);
+  if (st != EXZ_OK) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    free_job(job);
+    return st;
+  }
+  *out = job;
+  return EXZ_OK;
+}
+
+exz_status exz_job_submit(exz_ctx *ctx, const exz_field *field, void *stream, exz_job **out) {
+  return job_begin(ctx, field, stream, out);
 }
 
 exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t iters,
@@ -770,7 +885,19 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   if (njobs == 0) return EXZ_OK;
   hipStream_t s = (hipStream_t)stream;
   HIP_OR_FAIL_B(hipSetDevice(ctx->device));
-  const size_t nf = (size_t)njobs;
+  reap(ctx);
+  // the jobs that are set up take part; a submitted job whose phase A has
+  // ended gets its phase B issued now (failed ones and those still in phase
+  // A sit this step out)
+  std::vector<exz_job *> in;
+  in.reserve((size_t)njobs);
+  for (int32_t k = 0; k < njobs; ++k) {
+    if (!jobs[k]) return fail_b(ctx, EXZ_E_INVALID, "null job");
+    (void)job_advance(jobs[k]);
+    if (jobs[k]->phase == 1) in.push_back(jobs[k]);
+  }
+  if (in.empty()) return EXZ_OK;
+  const size_t nf = in.size();
   const size_t lw = list_words(nf);
   const size_t bytes = nf * sizeof(FieldDev) + NLISTS * lw * sizeof(uint32_t);
   // staging of the previous step must have been consumed before reuse
@@ -793,8 +920,7 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   BatchShape shape = batch_shape(ctx);
   bool have3 = false, have2 = false;
   for (size_t k = 0; k < nf; ++k) {
-    if (!jobs[k]) return fail_b(ctx, EXZ_E_INVALID, "null job");
-    const FieldDev &fd = jobs[k]->fd;
+    const FieldDev &fd = in[k]->fd;
     int &ty = fd.nz > 1 ? shape.ty3 : shape.ty2, &tz = fd.nz > 1 ? shape.tz3 : shape.tz2;
     bool &have = fd.nz > 1 ? have3 : have2;
     if (!have) {
@@ -814,7 +940,7 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   if (ctx->step_done) HIP_OR_FAIL_B(hipStreamWaitEvent(s, ctx->step_done, 0));
   else HIP_OR_FAIL_B(hipEventCreateWithFlags(&ctx->step_done, hipEventDisableTiming));
   for (size_t k = 0; k < nf; ++k) {
-    exz_job *job = jobs[k];
+    exz_job *job = in[k];
     if (!job->joined) {
       HIP_OR_FAIL_B(hipStreamWaitEvent(s, job->ready, 0));
       job->joined = true;
@@ -837,17 +963,26 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   const int grid_ord = batch_grid(ords, 0, 8);
   issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, (int)nf, grid_apply, grid_ord, s);
   HIP_OR_FAIL_B(hipGetLastError());
+  // each job's state after the step, into the next of its host slots, for
+  // exz_job_query (which reads the latest slot whose copy has ended)
+  for (exz_job *job : in) {
+    const int slot = (job->slot + 1) % exz_job::NSTATE;
+    HIP_OR_FAIL_B(hipMemcpyAsync(&job->pinned->st[slot], job->fd.st, sizeof(exz::State),
+                                 hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL_B(hipEventRecord(job->polled[slot], s));
+    job->recorded[slot] = true;
+    job->slot = slot;
+  }
   HIP_OR_FAIL_B(hipEventRecord(ctx->step_done, s));
   return EXZ_OK;
 }
 
-exz_status exz_job_poll(exz_job *job, int32_t *done, exz_result *result) {
-  if (!job || !done) return EXZ_E_INVALID;
-  exz_ctx *ctx = job->ctx;
-  HIP_OR_FAIL_B(hipSetDevice(ctx->device));
-  State hs;
-  HIP_OR_FAIL_B(hipMemcpyAsync(&hs, job->fd.st, sizeof(State), hipMemcpyDeviceToHost, job->last));
-  HIP_OR_FAIL_B(hipStreamSynchronize(job->last));
+}  // extern "C"
+
+namespace {
+
+// The result fields of a job from a copy of its device state.
+void fill_result(exz_job *job, const exz::State &hs, int32_t *done, exz_result *result) {
   *done = hs.done != RUNNING;
   exz_result &r = job->result;
   r.iterations = hs.iterations;
@@ -859,20 +994,62 @@ exz_status exz_job_poll(exz_job *job, int32_t *done, exz_result *result) {
   r.residual_violations = hs.residual;
   r.status = hs.done == STUCK ? EXZ_W_STUCK : hs.done == MAXITERS ? EXZ_W_MAX_ITERS : EXZ_OK;
   if (result) *result = r;
+}
+
+exz_status job_failure(exz_job *job, int32_t *done) {
+  *done = 1;
+  job->ctx->last_error = job->failed_msg;
+  return job->failed;
+}
+
+}  // namespace
+
+extern "C" {
+
+exz_status exz_job_poll(exz_job *job, int32_t *done, exz_result *result) {
+  if (!job || !done) return EXZ_E_INVALID;
+  exz_ctx *ctx = job->ctx;
+  HIP_OR_FAIL_B(hipSetDevice(ctx->device));
+  if (job->phase == 0) {  // a submitted job: finish its set-up first
+    HIP_OR_FAIL_B(hipEventSynchronize(job->a_done));
+    (void)job_advance(job);
+  }
+  if (job->phase == 2) return job_failure(job, done);
+  State hs;
+  HIP_OR_FAIL_B(hipMemcpyAsync(&hs, job->fd.st, sizeof(State), hipMemcpyDeviceToHost, job->last));
+  HIP_OR_FAIL_B(hipStreamSynchronize(job->last));
+  fill_result(job, hs, done, result);
+  return EXZ_OK;
+}
+
+exz_status exz_job_query(exz_job *job, int32_t *done, exz_result *result) {
+  if (!job || !done) return EXZ_E_INVALID;
+  *done = 0;
+  exz_ctx *ctx = job->ctx;
+  HIP_OR_FAIL_B(hipSetDevice(ctx->device));
+  (void)job_advance(job);
+  if (job->phase == 2) return job_failure(job, done);
+  if (job->phase == 0 || job->slot < 0) return EXZ_OK;  // not stepped yet
+  for (int t = 0, s = job->slot; t < exz_job::NSTATE;
+       ++t, s = (s + exz_job::NSTATE - 1) % exz_job::NSTATE) {
+    if (!job->recorded[s]) continue;
+    const hipError_t q = hipEventQuery(job->polled[s]);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return fail_b(ctx, EXZ_E_HIP, "hipEventQuery failed");
+    fill_result(job, job->pinned->st[s], done, result);
+    return EXZ_OK;
+  }
   return EXZ_OK;
 }
 
 exz_status exz_job_release(exz_job *job) {
   if (!job) return EXZ_OK;
-  (void)hipSetDevice(job->ctx->device);
-  if (job->last) (void)hipStreamSynchronize(job->last);
-  if (job->ready) {
-    (void)hipEventSynchronize(job->ready);
-    (void)hipEventDestroy(job->ready);
-  }
-  job->A.release();
-  job->B.release();
-  delete job;
+  exz_ctx *ctx = job->ctx;
+  (void)hipSetDevice(ctx->device);
+  // the workspace goes back once the device is done with it
+  if (job_quiet(job)) free_job(job);
+  else ctx->graveyard.push_back(job);
+  reap(ctx);
   return EXZ_OK;
 }
 

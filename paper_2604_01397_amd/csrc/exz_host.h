@@ -59,6 +59,15 @@ struct Layout {
 exz_status prepare_field(exz_ctx *ctx, const exz_params *p, FieldDev &fd);
 exz_status setup_field(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_hat, void *g_out,
                        uint8_t *cnt_io, int64_t max_iters, Arena &A, Arena &B, hipStream_t s);
+// The two halves of setup_field.  Phase A (per-vertex work: validation,
+// reference topology, critical-point bitmask and counts) is issued on s and
+// ends with copies of the device state into *h_state and of the number of
+// critical points into *h_k (both pinned); phase B (the critical points in
+// f's order) needs that number.
+exz_status setup_phase_a(exz_ctx *ctx, FieldDev &fd, const void *f, const void *g_hat,
+                         void *g_out, uint8_t *cnt_io, int64_t max_iters, Arena &A, hipStream_t s,
+                         State *h_state, uint32_t *h_k);
+exz_status setup_phase_b(exz_ctx *ctx, FieldDev &fd, uint32_t K, Arena &B, hipStream_t s);
 exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void *g_out,
                             uint8_t *cnt_io, const exz_params *params, exz_result *res,
                             hipStream_t s, Arena &A, Arena &B, Arena &C, bool profile);
@@ -134,7 +143,12 @@ struct exz_ctx {
   std::vector<hipEvent_t> events;
   hipEvent_t ev_start = nullptr, ev_setup = nullptr, ev_end = nullptr;
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
+  // released jobs whose device work had not ended yet; freed once it has
+  std::vector<exz_job *> graveyard;
 };
+
+// Frees every job of ctx's graveyard (the device must be idle).
+void free_graveyard(exz_ctx *ctx);
 
 // A serving job: one field whose correction state stays on the device
 // between exz_step calls.
@@ -148,4 +162,25 @@ struct exz_job {
   bool finished = false;
   hipEvent_t ready = nullptr;  // set-up done (recorded on the creation stream)
   bool joined = false;         // a step has waited for `ready`
+  // exz_job_submit: phase A of the set-up is in flight until a_done; phase
+  // B is issued on create_stream by the first exz_step / exz_job_query /
+  // exz_job_poll that finds it ended
+  int phase = 1;               // 0 phase A in flight, 1 set up, 2 failed
+  exz_status failed = EXZ_OK;  // phase 2: the status, and its message
+  std::string failed_msg;
+  hipEvent_t a_done = nullptr;
+  hipStream_t create_stream = nullptr;
+  // The state after each step goes to one of NSTATE host slots in turn.
+  // exz_step lets the host run one step ahead (it waits until the previous
+  // step has started), so of the steps issued, the latest two may still run
+  // and the third latest has ended: three slots always hold an ended one.
+  static constexpr int NSTATE = 3;
+  struct Pinned {
+    exz::State st[NSTATE];      // phase A's state (slot 0), then the state after each step
+    uint32_t k;                // number of critical points
+  };
+  Pinned *pinned = nullptr;    // host-pinned
+  hipEvent_t polled[NSTATE] = {};  // after the copy into st[s] of its last steps
+  bool recorded[NSTATE] = {};
+  int slot = -1;               // slot of the latest step's copy (-1: not stepped yet)
 };

@@ -20,9 +20,11 @@ E_INVALID, E_NONFINITE, E_BOUND, E_NOMEM, E_HIP, E_BUSY = -1, -2, -3, -4, -5, -6
 
 EXPORTS = (
     "exz_ctx_create", "exz_ctx_destroy", "exz_ctx_set_option", "exz_ctx_bytes_in_use",
-    "exz_workspace_bytes", "exz_correct", "exz_correct_host", "exz_correct_noalloc",
+    "exz_workspace_bytes", "exz_workspace_bytes_k", "exz_correct", "exz_correct_host",
+    "exz_correct_noalloc",
     "exz_correct_batch",
-    "exz_job_create", "exz_step", "exz_job_poll", "exz_job_release", "exz_job_bytes",
+    "exz_job_create", "exz_job_submit", "exz_step", "exz_job_poll", "exz_job_query",
+    "exz_job_release", "exz_job_bytes",
     "exz_status_string", "exz_last_error", "exz_debug_bounds", "exz_debug_targets",
 )
 
@@ -90,9 +92,13 @@ def load(path: str | None = None):
     L.exz_ctx_set_option.argtypes = [p, ctypes.c_char_p, i64]
     L.exz_workspace_bytes.argtypes = [ctypes.POINTER(Params)]
     L.exz_workspace_bytes.restype = ctypes.c_size_t
+    L.exz_workspace_bytes_k.argtypes = [ctypes.POINTER(Params), ctypes.c_int64]
+    L.exz_workspace_bytes_k.restype = ctypes.c_size_t
     L.exz_correct.argtypes = [p, p, p, p, p, ctypes.POINTER(Params), ctypes.POINTER(Result), p]
     L.exz_correct_batch.argtypes = [p, ctypes.POINTER(Field), i32, ctypes.POINTER(Result), p]
     L.exz_job_create.argtypes = [p, ctypes.POINTER(Field), p, ctypes.POINTER(p)]
+    L.exz_job_submit.argtypes = [p, ctypes.POINTER(Field), p, ctypes.POINTER(p)]
+    L.exz_job_query.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(Result)]
     L.exz_step.argtypes = [p, ctypes.POINTER(p), i32, i32, p]
     L.exz_job_poll.argtypes = [p, ctypes.POINTER(i32), ctypes.POINTER(Result)]
     L.exz_job_release.argtypes = [p]
@@ -106,8 +112,9 @@ def load(path: str | None = None):
     L.exz_debug_targets.argtypes = [p, p, p, ctypes.POINTER(Params), p, ctypes.POINTER(i64), p]
     for name in ("exz_ctx_create", "exz_ctx_destroy", "exz_ctx_set_option", "exz_correct",
                  "exz_correct_host", "exz_correct_noalloc",
-                 "exz_correct_batch", "exz_job_create", "exz_step", "exz_job_poll",
-                 "exz_job_release", "exz_debug_bounds", "exz_debug_targets"):
+                 "exz_correct_batch", "exz_job_create", "exz_job_submit", "exz_step",
+                 "exz_job_poll", "exz_job_query", "exz_job_release", "exz_debug_bounds",
+                 "exz_debug_targets"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -324,6 +331,15 @@ class Context:
 
         The job keeps references to its tensors until it is released.
         ``g_out`` may be ``g_hat`` (in place)."""
+        return self._job("exz_job_create", f, g_hat, xi, n_steps, max_iters, g_out, cnt, stream)
+
+    def job_submit(self, f, g_hat, xi, n_steps=5, max_iters=0, g_out=None, cnt=None,
+                   stream=None):
+        """job_create without waiting for the set-up (exz_job_submit): a bad
+        field is reported later, by Job.query / Job.poll."""
+        return self._job("exz_job_submit", f, g_hat, xi, n_steps, max_iters, g_out, cnt, stream)
+
+    def _job(self, entry, f, g_hat, xi, n_steps, max_iters, g_out, cnt, stream):
         import torch
         _check_tensor(f)
         _check_tensor(g_hat, f)
@@ -339,7 +355,8 @@ class Context:
         fl.g_out = g_out.data_ptr()
         fl.cnt_io = cnt.data_ptr()
         h = ctypes.c_void_p()
-        st = self.lib.exz_job_create(self.h, ctypes.byref(fl), _stream_ptr(stream), ctypes.byref(h))
+        st = getattr(self.lib, entry)(self.h, ctypes.byref(fl), _stream_ptr(stream),
+                                      ctypes.byref(h))
         if st != OK:
             raise ExactzError(st, self.last_error())
         return Job(self, h, (f, g_hat, g_out, cnt))
@@ -392,9 +409,17 @@ class Job:
 
     def poll(self):
         """(done, result dict); waits for the work issued for this job."""
+        return self._state("exz_job_poll")
+
+    def query(self):
+        """(done, result dict) after the job's latest step whose work has
+        ended; never waits (exz_job_query)."""
+        return self._state("exz_job_query")
+
+    def _state(self, entry):
         done = ctypes.c_int32()
         r = Result()
-        st = self.ctx.lib.exz_job_poll(self.h, ctypes.byref(done), ctypes.byref(r))
+        st = getattr(self.ctx.lib, entry)(self.h, ctypes.byref(done), ctypes.byref(r))
         if st != OK:
             raise ExactzError(st, self.ctx.last_error())
         return bool(done.value), r.to_dict()
@@ -426,8 +451,10 @@ def job_bytes(shape_xyz, dtype=F32, xi=1e-3, n_steps=5):
     return int(lib.exz_job_bytes(ctypes.byref(p)))
 
 
-def workspace_bytes(shape_xyz, dtype=F32, xi=1e-3, n_steps=5, mode=REFORMULATED, certify=False):
-    """exz_workspace_bytes for a field of the given (nx[, ny[, nz]]) shape."""
+def workspace_bytes(shape_xyz, dtype=F32, xi=1e-3, n_steps=5, mode=REFORMULATED, certify=False,
+                    num_critical=None):
+    """exz_workspace_bytes for a field of the given (nx[, ny[, nz]]) shape
+    (exz_workspace_bytes_k when num_critical is given)."""
     lib = load()
     p = Params()
     p.ndim = len(shape_xyz)
@@ -439,6 +466,8 @@ def workspace_bytes(shape_xyz, dtype=F32, xi=1e-3, n_steps=5, mode=REFORMULATED,
     p.n_steps = n_steps
     p.event_mode = mode
     p.certify = int(certify)
+    if num_critical is not None:
+        return int(lib.exz_workspace_bytes_k(ctypes.byref(p), int(num_critical)))
     return int(lib.exz_workspace_bytes(ctypes.byref(p)))
 
 

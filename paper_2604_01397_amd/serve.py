@@ -97,7 +97,8 @@ class Server:
 
     def __init__(self, executor, budget_bytes: int, max_active: int = 64,
                  iters_per_step: int = 2, clock=time.perf_counter, sleep=time.sleep,
-                 keep_outputs: bool = False):
+                 keep_outputs: bool = False, progress: Optional[Callable[[dict], None]] = None,
+                 progress_every: float = 10.0):
         if budget_bytes <= 0 or max_active < 1 or iters_per_step < 1:
             raise ValueError("budget, max_active and iters_per_step must be positive")
         self.ex = executor
@@ -107,6 +108,8 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.keep_outputs = keep_outputs
+        self.progress = progress
+        self.progress_every = progress_every
 
     def run(self, specs) -> Report:
         pending = collections.deque(sorted(specs, key=lambda s: (s.arrival, s.job_id)))
@@ -115,9 +118,15 @@ class Server:
         records = {s.job_id: JobRecord(s) for s in pending}
         used = 0
         max_active = max_bytes = steps = 0
+        finished = 0
         t0 = self.clock()
+        last_report = 0.0
         while pending or queue or active:
             now = self.clock() - t0
+            if self.progress and now - last_report >= self.progress_every:
+                last_report = now
+                self.progress({"t": round(now, 1), "finished": finished, "active": len(active),
+                               "queued": len(queue), "pending": len(pending), "steps": steps})
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             # the batched step of the active jobs goes out first, so the
@@ -152,7 +161,14 @@ class Server:
                 continue
             still = []
             for rec, h, need in active:
-                done, res = self.ex.poll(h)
+                try:
+                    done, res = self.ex.poll(h)
+                except Exception as e:  # a job whose set-up failed (bad input)
+                    rec.error = "%s: %s" % (type(e).__name__, e)
+                    self.ex.finish(h)
+                    used -= need
+                    finished += 1
+                    continue
                 if done:
                     rec.completed = self.clock() - t0
                     rec.result = res
@@ -160,7 +176,14 @@ class Server:
                     if self.keep_outputs:
                         rec.outputs = out
                     used -= need
+                    finished += 1
                 else:
+                    # the admission estimate gives way to the real footprint
+                    # once the job's set-up has counted its critical points
+                    real = getattr(self.ex, "footprint_of", lambda *_: None)(rec.spec, res)
+                    if real is not None and real != need:
+                        used += real - need
+                        need = real
                     still.append((rec, h, need))
             active = still
         wall = self.clock() - t0
@@ -171,13 +194,17 @@ class DeviceExecutor:
     """Runs jobs through the library's job API on one device.
 
     Inputs are materialised by ``spec.make(stream)`` on a side stream, then
-    the job is created there (its set-up overlaps the batched steps issued
-    on the main stream); the corrected field is written in place over the
-    job's copy of g_hat.
+    the job is submitted there (exz_job_submit: its set-up overlaps the
+    batched steps issued on the main stream, and nothing waits for it); the
+    corrected field is written in place over the job's copy of g_hat.
+    ``poll`` never waits (exz_job_query), so the host keeps the main stream
+    fed; exz_step itself lets the host run at most about one step ahead.
+    With ``blocking=True`` the executor uses exz_job_create / exz_job_poll
+    instead (the host waits for each set-up and each step).
     """
 
     def __init__(self, ctx, n_steps: int = 5, keep_outputs: bool = False, tuned: bool = False,
-                 tune_cache: Optional[str] = None):
+                 tune_cache: Optional[str] = None, blocking: bool = False):
         import torch
 
         from . import exactz
@@ -188,6 +215,7 @@ class DeviceExecutor:
         self.keep = keep_outputs
         self.main = torch.cuda.Stream()
         self.side = torch.cuda.Stream()
+        self.blocking = blocking
         # batched launch options from the autotune table's serving entry, set
         # once before the first job (a job keeps the box shape it was created
         # with, and the jobs of one step must share it)
@@ -197,27 +225,40 @@ class DeviceExecutor:
             key = autotune.make_serving_key(autotune.device_arch(ctx.device))
             self.tuned_options = autotune.apply_batch_options(ctx, key, tune_cache)
 
-    def footprint(self, spec) -> int:
+    # critical points per vertex assumed at admission; the real count, known
+    # once a job's set-up has run, replaces the estimate (footprint_of)
+    CP_FRACTION = 0.25
+
+    def footprint(self, spec, num_critical=None) -> int:
         shape_xyz = tuple(reversed(spec.shape))
         n = int(np.prod(spec.shape))
         b = spec.field_bytes // max(n, 1)
-        work = self.exactz.job_bytes(shape_xyz, self.exactz.F32 if b == 4 else self.exactz.F64,
-                                     n_steps=self.n_steps)
+        k = int(self.CP_FRACTION * n) if num_critical is None else int(num_critical)
+        work = self.exactz.workspace_bytes(shape_xyz, self.exactz.F32 if b == 4 else self.exactz.F64,
+                                           n_steps=self.n_steps, num_critical=min(k, n))
         return work + 2 * spec.field_bytes + n  # f, g (in place), counts
+
+    def footprint_of(self, spec, result) -> Optional[int]:
+        """The job's real footprint once its set-up has run, else None."""
+        k = (result or {}).get("num_critical", 0)
+        return self.footprint(spec, k) if k else None
 
     def start(self, spec):
         with self.torch.cuda.stream(self.side):
             f, g, xi = spec.make(self.side)
             cnt = self.torch.zeros(f.shape, dtype=self.torch.uint8, device=f.device)
-        job = self.ctx.job_create(f, g, xi, n_steps=self.n_steps, g_out=g, cnt=cnt,
-                                  stream=self.side)
-        return job
+        # the steps on the main stream use these buffers too: the caching
+        # allocator must not hand them out again before that work has ended
+        for t in (f, g, cnt):
+            t.record_stream(self.main)
+        create = self.ctx.job_create if self.blocking else self.ctx.job_submit
+        return create(f, g, xi, n_steps=self.n_steps, g_out=g, cnt=cnt, stream=self.side)
 
     def step(self, handles, iters):
         self.ctx.step(handles, iters, stream=self.main)
 
     def poll(self, job):
-        return job.poll()
+        return job.poll() if self.blocking else job.query()
 
     def finish(self, job):
         out = (job.g_out, job.cnt) if self.keep else None

@@ -372,9 +372,15 @@ def eps_for_device(f, rel: float) -> float:
     return e
 
 
-def quantize_uniform_device(f, eps: float):
+def quantize_uniform_device(f, eps: float, checked: bool = True):
     """quantize_uniform() of a float32 device tensor (same rounding, same band
-    enforcement: |g - f| <= eps exactly)."""
+    enforcement: |g - f| <= eps exactly).
+
+    With ``checked=False`` nothing waits for the device: two rounds of band
+    enforcement run unconditionally (a round that finds nothing outside the
+    band changes nothing, so the result equals the checked one whenever two
+    rounds suffice, which one ulp of float32 rounding always does; a value
+    still outside the band would be rejected by the library's validation)."""
     import torch
 
     if f.dtype != torch.float32:
@@ -384,9 +390,11 @@ def quantize_uniform_device(f, eps: float):
     b = torch.full((), 2.0 * eps, dtype=torch.float64, device=f.device)
     q = torch.round(f.double() / b) * b  # round half to even, as np.rint
     g = q.to(torch.float32)
-    for _ in range(8):
+    for _ in range(8 if checked else 2):
         bad = (g.double() - f.double()).abs() > eps
-        if not bool(bad.any()):
+        if checked and not bool(bad.any()):
             return g
         g = torch.where(bad, torch.nextafter(g, f), g)
+    if not checked:
+        return g
     raise RuntimeError("band enforcement did not converge")

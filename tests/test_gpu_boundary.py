@@ -98,3 +98,30 @@ def test_context_budget():
     finally:
         ctx.close()
         free.close()
+
+
+def test_workspace_bytes_k_prices_a_job():
+    """exz_workspace_bytes_k with a job's real number of critical points is
+    what the job's set-up reserves (the context adds at most an eighth plus
+    4 KiB of slack to each of its two reservations)."""
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = exactz.Context(0)
+    try:
+        c = synth.case_grf3d(48, seed=71, rel=1e-3)
+        f = torch.from_numpy(c.f).cuda()
+        g = torch.from_numpy(c.g_hat).cuda()
+        before = ctx.bytes_in_use()
+        job = ctx.job_create(f, g.clone(), c.xi)
+        delta = ctx.bytes_in_use() - before
+        _, r = job.poll()
+        k = r["num_critical"]
+        print("job reserved", delta, "bytes, K =", k, flush=True)
+        want = exactz.workspace_bytes((48, 48, 48), num_critical=k)
+        assert 0 < k < 48 ** 3
+        assert want <= delta <= want + want // 8 + 2 * 4096 + 512
+        assert want < exactz.workspace_bytes((48, 48, 48))  # the worst case (K = n)
+        job.release()
+    finally:
+        ctx.close()

@@ -25,11 +25,13 @@ def _cases():
     ]
 
 
-@pytest.mark.parametrize("tuned", [False, True])
-def test_served_jobs_equal_alone_runs(tuned, monkeypatch):
-    """With tuned=True the executor sets batched launch options per step from
-    the autotune table (here a table that answers every key with non-default
-    boxes, grid caps and item size)."""
+@pytest.mark.parametrize("tuned,blocking", [(False, False), (True, False), (False, True)])
+def test_served_jobs_equal_alone_runs(tuned, blocking, monkeypatch):
+    """With tuned=True the executor sets the batched launch options of the
+    autotune table's serving entry (here a table that answers every key with
+    non-default boxes, grid caps and item size); with blocking=False (the
+    default) jobs are submitted and polled without waiting (exz_job_submit,
+    exz_job_query), with blocking=True created and polled with waits."""
     from paper_2604_01397_amd import autotune, exactz
     from paper_2604_01397_amd.serve import DeviceExecutor, JobSpec, Server
     if not torch.cuda.is_available():
@@ -49,7 +51,7 @@ def test_served_jobs_equal_alone_runs(tuned, monkeypatch):
             # all arrive at once, so that the budget (not the timing) decides how
             # many run together
             specs.append(JobSpec(j, 0.0, c.f.shape, c.f.nbytes, make))
-        ex = DeviceExecutor(ctx, keep_outputs=True, tuned=tuned)
+        ex = DeviceExecutor(ctx, keep_outputs=True, tuned=tuned, blocking=blocking)
         # a budget of about three jobs: later arrivals wait for memory
         budget = 3 * max(ex.footprint(s) for s in specs)
         print("serving", len(specs), "jobs, budget", budget, flush=True)
@@ -141,5 +143,89 @@ def test_job_stepped_at_once_on_another_stream():
             assert torch.equal(j.g_out, g1) and torch.equal(j.cnt, c1), c.name
             assert r["iterations"] == r1["iterations"] and r["status"] == r1["status"]
             j.release()
+    finally:
+        ctx.close()
+
+
+def test_submitted_jobs_and_bad_input_reported_later():
+    """exz_job_submit returns before the set-up has run: jobs stepped at once
+    on another stream and followed with exz_job_query (which never waits)
+    end equal to exz_correct; a field outside the band is reported by the
+    query (done, EXZ_E_BOUND) and a step skips it."""
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = exactz.Context(0)
+    try:
+        cases = [synth.case_grf3d(40, seed=44, rel=1e-3), synth.case_grf3d(30, seed=45, rel=1e-3)]
+        s_create, s_step = torch.cuda.Stream(), torch.cuda.Stream()
+        jobs, ins = [], []
+        for c in cases:
+            with torch.cuda.stream(s_create):
+                f = torch.from_numpy(np.ascontiguousarray(c.f)).cuda()
+                g = torch.from_numpy(np.ascontiguousarray(c.g_hat)).cuda()
+            print("submit", c.name, flush=True)
+            jobs.append(ctx.job_submit(f, g.clone(), c.xi, stream=s_create))
+            ins.append((f, g))
+        fb = torch.zeros((8, 9), dtype=torch.float32, device="cuda")
+        gb = fb.clone()
+        gb[2, 3] = 0.5  # outside [f - xi, f + xi]
+        bad = ctx.job_submit(fb, gb, 0.125, stream=s_create)
+        done = [False] * len(jobs)
+        results = [None] * len(jobs)
+        for _ in range(400):
+            ctx.step(jobs + [bad], 2, stream=s_step)
+            for k, j in enumerate(jobs):
+                if not done[k]:
+                    done[k], results[k] = j.query()
+            if all(done):
+                break
+        assert all(done)
+        with pytest.raises(exactz.ExactzError) as e:
+            bad.query()
+        assert e.value.status == exactz.E_BOUND
+        bad.release()
+        s_step.synchronize()
+        for c, j, r, (f, g) in zip(cases, jobs, results, ins):
+            g1, c1, r1 = ctx.correct(f, g, c.xi)
+            torch.cuda.synchronize()
+            assert torch.equal(j.g_out, g1) and torch.equal(j.cnt, c1), c.name
+            for k in ("iterations", "edited_vertices", "edit_ops", "status"):
+                assert r[k] == r1[k], (c.name, k)
+            j.release()
+    finally:
+        ctx.close()
+
+
+def test_query_sees_completion_while_steps_queue_up():
+    """The host runs one step ahead of the device: with the device slowed
+    down before every step, the latest two steps are still in flight at each
+    query, and exz_job_query must still report the job done (it reads the
+    latest step whose work has ended)."""
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = exactz.Context(0)
+    try:
+        c = synth.case_grf3d(24, seed=46, rel=1e-3)
+        f = torch.from_numpy(np.ascontiguousarray(c.f)).cuda()
+        g = torch.from_numpy(np.ascontiguousarray(c.g_hat)).cuda()
+        s = torch.cuda.Stream()
+        job = ctx.job_create(f, g.clone(), c.xi, stream=s)
+        done, r, n = False, None, 0
+        for n in range(300):
+            with torch.cuda.stream(s):
+                torch.cuda._sleep(2_000_000)  # a bounded spin: the device falls behind
+            ctx.step([job], 1, stream=s)
+            done, r = job.query()
+            if done:
+                break
+        print("reported done after", n + 1, "steps", flush=True)
+        assert done
+        s.synchronize()
+        g1, c1, r1 = ctx.correct(f, g, c.xi)
+        torch.cuda.synchronize()
+        assert torch.equal(job.g_out, g1) and r["iterations"] == r1["iterations"]
+        job.release()
     finally:
         ctx.close()

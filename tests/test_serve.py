@@ -158,3 +158,45 @@ def test_bad_configuration_rejected():
         Server(SimExecutor(clk), budget_bytes=0)
     with pytest.raises(ValueError):
         Server(SimExecutor(clk), budget_bytes=10, iters_per_step=0)
+
+
+def test_admission_estimate_gives_way_to_the_real_footprint():
+    """An executor that reports a job's real footprint after its set-up:
+    the server's accounting follows it (here the real one is half the
+    estimate, so a third job fits once the first two have reported)."""
+    from paper_2604_01397_amd.serve import JobSpec, Server
+
+    class Ex:
+        def __init__(self):
+            self.polls = {}
+            self.started = []
+
+        def footprint(self, spec):
+            return 100
+
+        def footprint_of(self, spec, res):
+            return 50 if res.get("num_critical") else None
+
+        def start(self, spec):
+            self.started.append(spec.job_id)
+            self.polls[spec.job_id] = 0
+            return spec.job_id
+
+        def step(self, handles, iters):
+            pass
+
+        def poll(self, h):
+            self.polls[h] += 1
+            return self.polls[h] > 3, {"num_critical": 7}
+
+        def finish(self, h):
+            return None
+
+    ex = Ex()
+    specs = [JobSpec(j, 0.0, (4, 4, 4), 256) for j in range(3)]
+    rep = Server(ex, 200, max_active=8, iters_per_step=1, sleep=lambda t: None).run(specs)
+    s = rep.summary()
+    assert s["completed"] == 3
+    # two admitted at 100 each; after their first poll they count 50 each,
+    # so the third is admitted before either finishes
+    assert rep.max_active == 3
