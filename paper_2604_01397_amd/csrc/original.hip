@@ -4,14 +4,17 @@
 // extremum its integral paths select: a join saddle (its lower link has two
 // or more components) selects the highest minimum reached by steepest descent
 // from its lower neighbours, a split saddle the lowest maximum reached by
-// steepest ascent from its upper neighbours (Sec. 3.1-3.2, 4.1 C3).  Paths
-// are resolved for every vertex at once by pointer jumping over the steepest
-// descent / ascent pointers: lab[v] <- lab[lab[v]] until nothing changes, a
-// logarithmic number of rounds in the longest path.  Descent labels occupy
-// lab[0, n), ascent labels lab[n, 2n) (stored as n + vertex).
+// steepest ascent from its upper neighbours (Sec. 3.1-3.2, 4.1 C3).  For f
+// (once, at set-up) and for the certificate the paths of every vertex are
+// resolved at once by pointer jumping over the steepest descent / ascent
+// pointers: lab[v] <- lab[lab[v]] until nothing changes, a logarithmic
+// number of rounds in the longest path.  Descent labels occupy lab[0, n),
+// ascent labels lab[n, 2n) (stored as n + vertex).
 //
-// Per iteration (original mode): the check pass also writes g's pointers,
-// the rounds resolve them, and one kernel applies (C2 with a thread per
+// Per iteration (original mode) only the paths from the link neighbours of
+// f's saddles are needed: the check pass writes g's pointers and one kernel
+// follows those paths on them (setting each start's pointer to its path's
+// end, so shared paths are walked once) and applies (C2 with a thread per
 // saddle in f's order, C3 with a thread per critical point in vertex order)
 //   C2  consecutive saddles of f keep their order in g (the lower one in f
 //       goes down when inverted), and
@@ -175,6 +178,47 @@ __global__ void k_select_f(FieldDev fd, const uint8_t *comp) {
   fd.sel_f[2 * k + 1] = comp[upper] >= 2 ? select_extremum(fd, F, fd.lab_f, s, upper, false) : NONE;
 }
 
+// End of the steepest descent (join) / ascent (split) path of g from v,
+// followed on g's pointers in lab (each pointer goes strictly down / up in
+// the simulated order, so a path has fewer than n steps; the bound only
+// guards the loop).  The start's pointer is then set to the end, which is
+// the end of its path too: later walks through it jump there at once, and a
+// walk that reads the old pointer reaches the same end.  (Halving every path
+// it walks, as union-find does, measured no faster: the walks are short and
+// the cost is the scattered loads of the saddles' neighbourhoods.)
+__device__ __forceinline__ uint32_t path_end(const FieldDev &fd, uint32_t *lab, uint32_t v,
+                                             bool join) {
+  uint32_t *P = join ? lab : lab + fd.n;
+  const uint32_t off = join ? 0u : (uint32_t)fd.n;
+  uint32_t u = v;
+  for (uint32_t step = 0; step < (uint32_t)fd.n; ++step) {
+    const uint32_t p = P[u] - off;
+    if (p == u) break;
+    u = p;
+  }
+  if (u != v) P[v] = u + off;
+  return u;
+}
+
+// select_extremum on g's pointers (the path ends followed on the fly).
+template <class T>
+__device__ __forceinline__ uint32_t select_extremum_g(const FieldDev &fd, const T *h, uint32_t *lab,
+                                                      uint32_t s, uint32_t sel, bool join) {
+  uint32_t best = NONE;
+  T bv = T(0);
+  for (int k = 0; k < NSLOT; ++k) {
+    if (!((sel >> k) & 1u)) continue;
+    const uint32_t t = path_end(fd, lab, (uint32_t)((int)s + fd.dlt[k]), join);
+    const T tv = h[t];
+    const bool better = best == NONE || (join ? sos_lt(bv, best, tv, t) : sos_lt(tv, t, bv, best));
+    if (better) {
+      best = t;
+      bv = tv;
+    }
+  }
+  return best;
+}
+
 template <class T>
 __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   const State *st = fd.st;
@@ -205,12 +249,12 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
     glower |= (uint32_t)sos_lt(G[j], j, gs, s) << q;
   }
   if (mf != NONE && glower) {
-    const uint32_t mg = select_extremum(fd, G, fd.lab, s, glower, true);
+    const uint32_t mg = select_extremum_g(fd, G, fd.lab, s, glower, true);
     if (mg != mf) mark_target(fd.tmark, mg);
   }
   const uint32_t gupper = vm & ~glower;
   if (Mf != NONE && gupper) {
-    const uint32_t Mg = select_extremum(fd, G, fd.lab, s, gupper, false);
+    const uint32_t Mg = select_extremum_g(fd, G, fd.lab, s, gupper, false);
     if (Mg != Mf) mark_target(fd.tmark, Mf);
   }
 }
@@ -296,9 +340,9 @@ hipError_t launch_original_setup(const FieldDev &fd, const uint8_t *comp, uint32
   return hipGetLastError();
 }
 
+// The check has just written g's pointers into fd.lab; the events follow
+// the paths they need from there (no labels of all 2n pointers resolved).
 hipError_t launch_original_events(const FieldDev &fd, const uint8_t *comp, hipStream_t s) {
-  hipError_t e = jump_all(fd, fd.lab, 2u * (uint32_t)fd.n, 1, s);
-  if (e != hipSuccess) return e;
   const int gk = (fd.K + 255) / 256 ? (fd.K + 255) / 256 : 1;
   if (fd.dtype == 0)
     hipLaunchKernelGGL(k_events<float>, dim3(gk), dim3(256), 0, s, fd, comp);
