@@ -190,6 +190,38 @@ def run_batched(torch, exactz, synth, reps=2):
             "iterations_max": int(max(its)), "iterations_mean": round(float(np.mean(its)), 2)}
 
 
+def run_float64(torch, exactz, synth, edge=512, reps=3):
+    """The 512^3 recipe in float64 (8-byte values, the paper's Table 2
+    sizes), with the shipped autotune table's options for its class."""
+    import numpy as np
+    from paper_2604_01397_amd import autotune
+    t0 = time.time()
+    case = synth.case_grf3d(edge, seed=2, slope=-11.0 / 3.0, rel=1e-4, dtype=np.float64,
+                            quantizer="lorenzo")
+    log("float64: generated %s in %.1f s" % (case.name, time.time() - t0))
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(case.f).to(dev)
+    g = torch.from_numpy(case.g_hat).to(dev)
+    g_out = torch.empty_like(f)
+    cnt = torch.zeros(f.shape, dtype=torch.uint8, device=dev)
+    ctx = exactz.Context(0)
+    opts = autotune.apply_options(ctx, f)
+    ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, _, res = ctx.correct(f, g, case.xi, g_out=g_out, cnt=cnt)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    ctx.close()
+    return {"workload": "%d^3 float64 GRF k^-11/3 (seed 2), Lorenzo quantiser, eps = 1e-4 range, "
+                        "N = 5, reformulated" % edge,
+            "ms_per_correction": round(ms, 3), "GBps": round(case.f.nbytes / (ms * 1e-3) / 1e9, 3),
+            "tuned_options": opts, "iterations": res["iterations"], "status": res["status"],
+            "status_text": STATUS_TEXT.get(res["status"], "?"),
+            "residual_violations": res["residual_violations"]}
+
+
 def run_serving(torch, exactz, synth, serve, jobs, rate, plain=True):
     """Continuous-batching server on a Poisson trace of (L+2)^3 float32 blocks,
     then (same jobs, same inputs) plain per-field exz_correct one after the
@@ -418,6 +450,9 @@ def main():
         from paper_2604_01397_amd import serve
         line["batched"] = run_batched(torch, exactz, synth)
         log("batched: %s" % line["batched"])
+        torch.cuda.empty_cache()
+        line["float64"] = run_float64(torch, exactz, synth, args.edge)
+        log("float64: %s" % line["float64"])
         torch.cuda.empty_cache()
         line["serving"] = run_serving(torch, exactz, synth, serve, args.serve_jobs, args.serve_rate,
                                       plain=not args.no_serve_plain)

@@ -9,6 +9,7 @@ them on the GPU and compares.  Nothing here touches a GPU.
     python tests/golden/make_fingerprints.py c2          # 512^3 float32 (minutes)
     python tests/golden/make_fingerprints.py c3 -w 8     # the 96 batched fields
     python tests/golden/make_fingerprints.py c4 -w 8     # serving jobs with L <= 256
+    python tests/golden/make_fingerprints.py orig -w 2   # original event constraints, 128^3, 192^3
 """
 from __future__ import annotations
 
@@ -37,13 +38,23 @@ def sha(a) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def fingerprint(case, name=None) -> dict:
+def fingerprint(case, name=None, mode=0) -> dict:
     t0 = time.perf_counter()
-    g, cnt, st, _ = oracle.correct(case.f, case.g_hat, case.xi)
+    g, cnt, st, _ = oracle.correct(case.f, case.g_hat, case.xi, mode=mode)
     dt = time.perf_counter() - t0
     return {"name": name or case.name, "shape": list(case.f.shape), "dtype": str(case.f.dtype),
             "xi": case.xi, "f_sha256": sha(case.f), "g_hat_sha256": sha(case.g_hat),
             "g_out_sha256": sha(g), "cnt_sha256": sha(cnt), "oracle_s": round(dt, 2), **st}
+
+
+ORIG_EDGES = (128, 192)
+
+
+def _orig_one(edge):
+    c = synth.case_grf3d(edge, seed=2, slope=-11.0 / 3.0, rel=1e-4, quantizer="lorenzo")
+    out = fingerprint(c, mode=1)
+    out["edge"] = edge
+    return out
 
 
 def _c3_one(spec):
@@ -62,7 +73,7 @@ def _c4_one(spec):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("config", choices=["c2", "c3", "c4"])
+    ap.add_argument("config", choices=["c2", "c3", "c4", "orig"])
     ap.add_argument("-w", "--workers", type=int, default=1)
     args = ap.parse_args()
     oracle.build()
@@ -71,6 +82,12 @@ def main():
         items = [fingerprint(synth.config2(512))]
         meta = {"workload": "512^3 float32 GRF k^-11/3 (seed 2), Lorenzo quantiser, "
                             "eps = 1e-4 range, N = 5, reformulated"}
+    elif args.config == "orig":
+        with mp.get_context("fork").Pool(args.workers) as pool:
+            items = pool.map(_orig_one, ORIG_EDGES, chunksize=1)
+        meta = {"workload": "GRF k^-11/3 (seed 2), Lorenzo quantiser, eps = 1e-4 range, N = 5, "
+                            "original event constraints (Sec. 4.2), float32, edges %s"
+                            % (ORIG_EDGES,)}
     elif args.config == "c3":
         specs = synth.config3_specs(96)
         with mp.get_context("fork").Pool(args.workers) as pool:

@@ -145,3 +145,18 @@ def test_c4_served_jobs_match_oracle():
         assert rep.summary()["completed"] == len(jobs)
     finally:
         ctx.close()
+
+
+@pytest.mark.timeout(300)
+def test_original_mode_matches_oracle_at_size(ctx):
+    """The original event constraints (Sec. 4.2) on 128^3 and 192^3 volumes of
+    the 512^3 workload's recipe, against the oracle's fingerprints."""
+    from paper_2604_01397_amd import exactz
+    for fp in _load("fingerprints_orig.json")["items"]:
+        c = synth.case_grf3d(fp["edge"], seed=2, slope=-11.0 / 3.0, rel=1e-4, quantizer="lorenzo")
+        assert _sha_host(c.f) == fp["f_sha256"] and _sha_host(c.g_hat) == fp["g_hat_sha256"]
+        print("original mode:", fp["edge"], flush=True)
+        g_out, cnt, res = ctx.correct(torch.from_numpy(c.f).cuda(), torch.from_numpy(c.g_hat).cuda(),
+                                      fp["xi"], mode=exactz.ORIGINAL)
+        torch.cuda.synchronize()
+        _check(fp, g_out, cnt, res, "original %d" % fp["edge"])
