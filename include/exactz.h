@@ -129,7 +129,8 @@ exz_status exz_ctx_destroy(exz_ctx *ctx);
  *   "profile"  0/1: record device events around every check pass and
  *              report check_launches / check_ms / check_vertices;
  *   "poll"     iterations issued between two host polls (1..256; default:
- *              adaptive, starting at 4);
+ *              adaptive: 4, then 8, then 16 while the last pass the host
+ *              saw changed more than n/64 values and 4 once it did not);
  *   "graph"    0/1: replay the iterations between polls from a captured
  *              hipGraph (batched calls; default 1);
  *   "tile"     check box 64 x tile_y x tile_z given as tile_y * 100 + tile_z;

@@ -693,16 +693,21 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
     HIP_OR_FAIL(hipEventRecord(ctx->poll_ev[slot], s));
     return EXZ_OK;
   };
+  // Adaptive chunks: 8 passes at first, then 16 while the latest known pass
+  // changed many values (the field cannot be near its fixpoint) and 4 once
+  // it did not, so that few launches run past the end.
   int slot = 0;
+  const State *known = nullptr;
   st = issue_chunk(slot);
   if (st != EXZ_OK) return st;
   for (;;) {
-    if (ctx->poll == 0) chunk = std::min(chunk * 2, 16);
+    if (ctx->poll == 0) chunk = !known ? 8 : known->busy ? 16 : 4;
     st = issue_chunk(1 - slot);
     if (st != EXZ_OK) return st;
     HIP_OR_FAIL(hipEventSynchronize(ctx->poll_ev[slot]));
     if (ctx->h_state[slot].done != RUNNING) break;
     if (ctx->h_state[slot].passes > cap) return fail(ctx, EXZ_E_HIP, "loop did not terminate");
+    known = &ctx->h_state[slot];
     slot = 1 - slot;
   }
   // the chunk still in flight ran past the fixpoint; its copy holds the final state

@@ -127,11 +127,12 @@ __global__ void __launch_bounds__(256) k_order_batch(const FieldDev *__restrict_
     if (fd.st->done) continue;
     const uint32_t r0 = (it - base[k]) * ORD_ITEM;
     const uint32_t lim = min((uint32_t)fd.K, r0 + ORD_ITEM + 1);  // the item's pairs only
+    const uint32_t tag = fd.st->tag;
     for (uint32_t j = 0; j < ORD_ITEM && r0 + j + 1 < lim; j += 1024) {
       if (fd.dtype == 0)
-        order_quad<float>(fd, r0 + j + 4 * threadIdx.x, lim, __lane_id() != 63);
+        order_quad<float>(fd, r0 + j + 4 * threadIdx.x, lim, __lane_id() != 63, tag);
       else
-        order_quad<double>(fd, r0 + j + 4 * threadIdx.x, lim, __lane_id() != 63);
+        order_quad<double>(fd, r0 + j + 4 * threadIdx.x, lim, __lane_id() != 63, tag);
     }
   }
 }

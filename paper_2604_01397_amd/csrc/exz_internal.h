@@ -50,6 +50,7 @@ struct State {
   int32_t noflag;         // this iteration's apply sets no box flags (the next check is dense)
   int32_t busy;           // the last apply changed many values (> n / 64): the next apply
                           // fetches every quad's counts ahead
+  uint32_t tag;           // mark byte of this pass's targets (1 .. MARK_TAGS)
   uint32_t jump[MAX_JUMP_ROUNDS];  // pointer-jumping round flags
   int64_t iterations;
   int64_t edit_ops;
@@ -126,7 +127,14 @@ __device__ __forceinline__ __attribute__((address_space(1))) P *glob(P *p) {
 // Adds vertex t to the target set: a plain byte store (every writer stores
 // the same value, so concurrent marks of one target need no atomics; the
 // cache keeps per-byte dirty masks, so neighbouring marks do not clash).
-__device__ __forceinline__ void mark_target(uint8_t *marks, uint32_t t) { glob(marks)[t] = 1; }
+// Target marks carry the pass that made them: a mark is the pass's tag byte
+// (1 .. MARK_TAGS, in turn; 0 = none), so apply takes the bytes equal to the
+// current tag and need not clear them.  The apply of a pass with the last
+// tag zeroes the whole array, so no mark outlives the cycle of tags.
+constexpr uint32_t MARK_TAGS = 254;
+__device__ __forceinline__ void mark_target(uint8_t *marks, uint32_t t, uint32_t tag) {
+  glob(marks)[t] = (uint8_t)tag;
+}
 
 // Simulation of Simplicity: (a, ia) < (b, ib).  Bitwise, not short-circuit,
 // so that the compiler emits straight-line compares instead of branches.

@@ -128,8 +128,9 @@ template <class T>
 __global__ void __launch_bounds__(256) k_order(FieldDev fd) {
   if (fd.st->done) return;
   const uint32_t K = (uint32_t)fd.K;
+  const uint32_t tag = fd.st->tag;
   for (uint32_t b = blockIdx.x * 1024u; b + 1 < K; b += gridDim.x * 1024u)
-    order_quad<T>(fd, b + 4u * threadIdx.x, K, __lane_id() != 63);
+    order_quad<T>(fd, b + 4u * threadIdx.x, K, __lane_id() != 63, tag);
 }
 
 // ApplyBoundedEdits over the target marks.
@@ -157,6 +158,7 @@ __global__ void __launch_bounds__(64) k_state_reset(State *st, int64_t max_iters
   st->dense = 1;
   st->noflag = 1;  // the first iterations change values in nearly every box
   st->busy = 1;
+  st->tag = 1;
   st->iterations = st->edit_ops = st->lossless_total = st->floor_total = st->edited_total = 0;
   st->targets_total = 0;
   st->residual = 0;
@@ -261,7 +263,7 @@ __global__ void k_targets_to_bytes(FieldDev fd, uint8_t *out) {
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   bool hit = false;
   if (t < (uint32_t)fd.n) {
-    hit = fd.tmark[t] != 0;
+    hit = fd.tmark[t] == fd.st->tag;
     out[t] = hit;
   }
   const uint32_t c = wave_sum((uint32_t)hit);

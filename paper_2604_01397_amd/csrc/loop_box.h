@@ -234,13 +234,13 @@ __device__ __forceinline__ uint32_t box_vertices(const FieldDev &fd, BoxOrigin o
 // Adds the targets named by vertex i's request mask r (bit s: the neighbour
 // in slot s, at offset dlt[s]; bit SELF: i itself).
 __device__ __forceinline__ void post_targets(const FieldDev &fd, const int32_t *dlt, uint32_t i,
-                                             uint32_t r) {
-  if ((r >> SELF) & 1u) mark_target(fd.tmark, i);
+                                             uint32_t r, uint32_t tag) {
+  if ((r >> SELF) & 1u) mark_target(fd.tmark, i, tag);
   r &= LOW_MASK;
   while (r) {
     const int s = __ffs(r) - 1;
     r &= r - 1;
-    mark_target(fd.tmark, (uint32_t)((int)i + dlt[s]));
+    mark_target(fd.tmark, (uint32_t)((int)i + dlt[s]), tag);
   }
 }
 
@@ -438,7 +438,8 @@ struct PlaneKeys {
 // those of check_vertex.
 template <int TY, int TZ>
 __device__ __forceinline__ void check_column_keys(const FieldDev &fd, CheckLds<float, TY, TZ> &L,
-                                                  BoxOrigin o, const uint32_t *refs, bool interior) {
+                                                  BoxOrigin o, const uint32_t *refs, bool interior,
+                                                  uint32_t tag) {
   using B = Box<TY, TZ>;
   constexpr int W = B::W;
   const int lx = threadIdx.x, ly = threadIdx.y;
@@ -496,7 +497,7 @@ __device__ __forceinline__ void check_column_keys(const FieldDev &fd, CheckLds<f
     if (col && z < fd.nz) {
       const uint32_t i = i0 + (uint32_t)k * plane;
       const uint32_t r = requests_of(L.conn, vm, asc, desc, lower, refs[k] & 255u, refs[k] >> 8);
-      if (r) post_targets(fd, L.dlt, i, r);
+      if (r) post_targets(fd, L.dlt, i, r, tag);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
         glob(fd.lab)[i] = (uint32_t)((int)i + L.dlt[desc]);
         glob(fd.lab)[fd.n + i] = (uint32_t)fd.n + (uint32_t)((int)i + L.dlt[asc]);
@@ -521,7 +522,7 @@ __device__ __forceinline__ void check_column_keys(const FieldDev &fd, CheckLds<f
 // The plain (double field) check of one box's columns, vertex by vertex.
 template <int TY, int TZ>
 __device__ __forceinline__ void check_column_plain(const FieldDev &fd, CheckLds<double, TY, TZ> &L,
-                                                   BoxOrigin o, bool interior) {
+                                                   BoxOrigin o, bool interior, uint32_t tag) {
   using B = Box<TY, TZ>;
   const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx;
   const int x = o.x0 + lx, y = o.y0 + ly;
@@ -539,7 +540,7 @@ __device__ __forceinline__ void check_column_plain(const FieldDev &fd, CheckLds<
       uint32_t av = 0, dv = 0;
       const uint32_t r = check_vertex<double>(fd, L.conn, L.dlt, c, -B::PLANE, B::PLANE, x, y, z, i,
                                               rf & 255u, rf >> 8, av, dv, interior);
-      if (r) post_targets(fd, L.dlt, i, r);
+      if (r) post_targets(fd, L.dlt, i, r, tag);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
         glob(fd.lab)[i] = dv;
         glob(fd.lab)[fd.n + i] = (uint32_t)fd.n + av;
@@ -556,6 +557,7 @@ __device__ __forceinline__ void check_column_plain(const FieldDev &fd, CheckLds<
 template <class T, int TY, int TZ>
 __device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, CheckLds<T, TY, TZ> &L) {
   constexpr bool keyed = sizeof(T) == 4;  // float fields: tie-free keys
+  const uint32_t tag = __builtin_amdgcn_readfirstlane(fd.st->tag);
   const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx;
   const int x = o.x0 + lx, y = o.y0 + ly;
   const bool col = x < fd.nx && y < fd.ny;
@@ -579,13 +581,13 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, Check
   if constexpr (keyed) {
     stage_rows<TY, TZ, float, TagKey, double>(fd, (const float *)fd.g, L.S, o);
     __syncthreads();
-    check_column_keys<TY, TZ>(fd, L, o, refs, interior);
+    check_column_keys<TY, TZ>(fd, L, o, refs, interior, tag);
   } else {
     stage_rows<TY, TZ, double, AsIs, double>(fd, (const double *)fd.g, L.S, o);
 #pragma unroll
     for (int k = 0; k < TZ; ++k) L.ref[k][tid] = refs[k];
     __syncthreads();
-    check_column_plain<TY, TZ>(fd, L, o, interior);
+    check_column_plain<TY, TZ>(fd, L, o, interior, tag);
   }
 }
 
@@ -632,7 +634,7 @@ template <> struct Vec4<double> {
 // the field's count (a batched item stops there).
 template <class T>
 __device__ __forceinline__ void order_quad(const FieldDev &fd, uint32_t r, uint32_t K,
-                                           bool next_in_lane) {
+                                           bool next_in_lane, uint32_t tag) {
   const T *V = (const T *)fd.cpr;
   T a[4];
   if (r + 4 <= K) {
@@ -649,7 +651,7 @@ __device__ __forceinline__ void order_quad(const FieldDev &fd, uint32_t r, uint3
     const T lo = a[c], hi = c < 3 ? a[c + 1] : nx;
     const bool below = (bw >> c) & 1u;
     if (r + c + 1 < K && (hi < lo || (hi == lo && below)))
-      mark_target(fd.tmark, glob(fd.cp_idx)[r + c]);
+      mark_target(fd.tmark, glob(fd.cp_idx)[r + c], tag);
   }
 }
 
@@ -689,7 +691,14 @@ __device__ __forceinline__ void mark_box_range(const FieldDev &fd, uint32_t x0, 
 constexpr int APPLY_BLOCK = 256;
 constexpr uint32_t APPLY_CHUNK = 4 * APPLY_BLOCK;
 
-// Target marks of vertices 4q .. 4q+3 (the mark array is padded).
+// The bytes of w equal to tag, as 1 (others 0).
+__device__ __forceinline__ uint32_t marks_of(uint32_t w, uint32_t tag) {
+  const uint32_t x = w ^ (tag * 0x01010101u);  // a marked byte is 0 here
+  const uint32_t t = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // bit 7: byte nonzero
+  return (~t & 0x80808080u) >> 7;
+}
+
+// Raw mark bytes of vertices 4q .. 4q+3 (the mark array is padded).
 __device__ __forceinline__ uint32_t quad_marks(const FieldDev &fd, uint32_t q) {
   return *glob(reinterpret_cast<const uint32_t *>(fd.tmark + 4u * q));
 }
@@ -800,7 +809,6 @@ __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, ui
                                               const QuadIn<T> &d, EditCount &ec) {
   T *G = (T *)fd.g;
   const T xiT = (T)fd.xiT, delta = (T)fd.delta;
-  *glob(reinterpret_cast<uint32_t *>(fd.tmark + v)) = 0;
   uint32_t moved = 0, cw = 0;
   T gn[4];
 #pragma unroll
@@ -880,10 +888,14 @@ __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uin
                                             uint32_t nq, EditCount &ec) {
   const bool flag = fd.frontier && !fd.st->noflag;
   const bool busy = fd.st->busy != 0;
+  const uint32_t tag = fd.st->tag;
+  const bool wipe = tag == MARK_TAGS;  // the last tag of the cycle: zero every mark
   QuadHead h = quad_head(fd, q0, nq, busy);
   for (uint32_t q = q0; q < nq; q += stride) {
     const QuadHead hn = quad_head(fd, q + stride, nq, busy);
     uint32_t moved = 0;
+    h.m = marks_of(h.m, tag);
+    if (wipe) *glob(reinterpret_cast<uint32_t *>(fd.tmark + 4u * q)) = 0;
     if (h.m) {
       QuadIn<T> d;
       load_quad<T>(fd, 4u * q, h, d);
@@ -922,7 +934,10 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
   State *st = fd.st;
   if (st->done) return;
   const int lane = threadIdx.x;
-  if (lane == 0) st->passes += 1;
+  if (lane == 0) {
+    st->passes += 1;
+    st->tag = st->tag % MARK_TAGS + 1;
+  }
   uint32_t v[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {

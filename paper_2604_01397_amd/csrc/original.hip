@@ -225,12 +225,13 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   if (st->done) return;
   const uint32_t k = blockIdx.x * 256 + threadIdx.x;
   const uint32_t ns = st->nsaddle;
+  const uint32_t tag = st->tag;
   const T *G = (const T *)fd.g;
   // C2: saddle order (thread k takes the k-th saddle in f's order)
   if (k + 1 < ns) {
     const uint32_t s = fd.cp_idx[fd.sad_rank[k]];
     const uint32_t sn = fd.cp_idx[fd.sad_rank[k + 1]];
-    if (sos_lt(G[sn], sn, G[s], s)) mark_target(fd.tmark, s);
+    if (sos_lt(G[sn], sn, G[s], s)) mark_target(fd.tmark, s, tag);
   }
   // C3: selected extrema along the integral paths of g (thread k takes the
   // critical point in vertex-order slot k)
@@ -250,12 +251,12 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   }
   if (mf != NONE && glower) {
     const uint32_t mg = select_extremum_g(fd, G, fd.lab, s, glower, true);
-    if (mg != mf) mark_target(fd.tmark, mg);
+    if (mg != mf) mark_target(fd.tmark, mg, tag);
   }
   const uint32_t gupper = vm & ~glower;
   if (Mf != NONE && gupper) {
     const uint32_t Mg = select_extremum_g(fd, G, fd.lab, s, gupper, false);
-    if (Mg != Mf) mark_target(fd.tmark, Mf);
+    if (Mg != Mf) mark_target(fd.tmark, Mf, tag);
   }
 }
 
