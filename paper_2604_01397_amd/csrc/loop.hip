@@ -66,6 +66,15 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   const BoxWalk w = box_walk(fd);
   const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
   uint32_t done_v = 0;  // vertices checked by this work-group (lead thread)
+  // The reformulated event constraints over all ranks, in items of four
+  // ranks per thread (the order test does not depend on this pass's
+  // check): a work-group takes one item after each box of a dense pass, so
+  // that the streaming of the critical-point values overlaps the other
+  // work-groups' arithmetic, and the rest after its boxes.
+  const bool order = fd.mode != 1 && fd.K > 1;
+  const uint32_t K = (uint32_t)fd.K, tag = st->tag;
+  const uint32_t tid = threadIdx.y * 64 + threadIdx.x, per = 4u * 64u * TY;
+  uint32_t ob = blockIdx.x * per;  // this work-group's next item
   if (!fd.frontier || st->dense) {
     // a dense pass consumes every box flag: clear them, so none is stale
     for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
@@ -76,6 +85,10 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
         if (fd.frontier) fd.bdirty[tile] = 0;
       }
       __syncthreads();
+      if (order && ob + 1 < K) {
+        order_quad<T>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
+        ob += gridDim.x * per;
+      }
     }
   } else {
     // Frontier pass: a box none of whose cells (halo included) changed in
@@ -108,6 +121,8 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
     }
   }
   if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
+  if (order)
+    for (; ob + 1 < K; ob += gridDim.x * per) order_quad<T>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
 }
 
 // Reference topology of f, box by box over the same persistent walk.
@@ -120,17 +135,6 @@ __global__ void __launch_bounds__(64 * TY) k_ref(FieldDev fd, const uint32_t *__
     ref_box<T, TY, TZ>(fd, box_of(fd, tile, TY, TZ), L);
     __syncthreads();
   }
-}
-
-// Reformulated event constraints: every pair of consecutive critical points
-// of f, in f's order.
-template <class T>
-__global__ void __launch_bounds__(256) k_order(FieldDev fd) {
-  if (fd.st->done) return;
-  const uint32_t K = (uint32_t)fd.K;
-  const uint32_t tag = fd.st->tag;
-  for (uint32_t b = blockIdx.x * 1024u; b + 1 < K; b += gridDim.x * 1024u)
-    order_quad<T>(fd, b + 4u * threadIdx.x, K, __lane_id() != 63, tag);
 }
 
 // ApplyBoundedEdits over the target marks.
@@ -200,12 +204,8 @@ static void launch_check_events(const FieldDev &fd, const uint32_t *conn, const 
   EXZ_BOX_SHAPES(EXZ_BOX_CHECK)
 #undef EXZ_BOX_CHECK
   if (ev1) (void)hipEventRecord(ev1, s);
-  if (fd.mode == 1) {
-    (void)launch_original_events(fd, comp, s);
-  } else if (fd.K > 1) {
-    const int g = (int)std::min<uint32_t>(((uint32_t)fd.K + 1022) / 1024, 16384u);
-    hipLaunchKernelGGL(k_order<T>, dim3(g), dim3(256), 0, s, fd);
-  }
+  // (the reformulated mode's order test runs inside the check kernel)
+  if (fd.mode == 1) (void)launch_original_events(fd, comp, s);
 }
 
 template <class T>
