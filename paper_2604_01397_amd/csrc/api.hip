@@ -382,7 +382,8 @@ exz_status exz_ctx_create(int device, size_t hbm_budget_bytes, exz_ctx **out) {
   exz_ctx *ctx = new exz_ctx();
   ctx->device = device;
   ctx->budget.limit = hbm_budget_bytes;
-  for (Arena *a : {&ctx->A, &ctx->B, &ctx->C, &ctx->BA, &ctx->BB, &ctx->H}) a->budget = &ctx->budget;
+  for (Arena *a : {&ctx->A, &ctx->B, &ctx->C, &ctx->BA, &ctx->BB, &ctx->BC, &ctx->H})
+    a->budget = &ctx->budget;
   // events of the single-field driver, created here so that a correction
   // call creates nothing
   if (hipEventCreate(&ctx->ev_start) != hipSuccess || hipEventCreate(&ctx->ev_setup) != hipSuccess ||
@@ -420,6 +421,7 @@ exz_status exz_ctx_destroy(exz_ctx *ctx) {
   ctx->C.release();
   ctx->BA.release();
   ctx->BB.release();
+  ctx->BC.release();
   ctx->H.release();
   if (ctx->step_host) (void)hipHostFree(ctx->step_host);
   if (ctx->step_dev) (void)hipFree(ctx->step_dev);

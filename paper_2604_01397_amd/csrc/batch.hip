@@ -30,22 +30,6 @@ struct ItemList {
   const uint32_t *base;       // [nfields + 1] item prefix
 };
 
-// Field slot of item `it` (largest k with base[k] <= it), found by walking
-// forward from slot k: a block (or thread) visits its items in increasing
-// order, so the walk is short and reads a few cached words.
-__device__ __forceinline__ uint32_t next_field(const uint32_t *base, uint32_t nf, uint32_t it,
-                                               uint32_t k) {
-  while (k + 1 < nf && base[k + 1] <= it) ++k;
-  return k;
-}
-
-// The same for a whole work-group (it is the same on every lane): the slot
-// is made explicitly wave-uniform so the field's descriptor is read with
-// scalar loads.
-__device__ __forceinline__ uint32_t next_field_uniform(const uint32_t *base, uint32_t nf,
-                                                       uint32_t it, uint32_t k) {
-  return __builtin_amdgcn_readfirstlane(next_field(base, nf, it, k));
-}
 
 // Check passes over the boxes of fields of one value type T.
 template <class T, int TY, int TZ>
@@ -265,7 +249,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
 // Device list buffers, capacity per list 2 + 2*nf + 1 words: boxes of 3D
 // float32 / 3D float64 / 2D-1D float32 / 2D-1D float64 fields, finalize (one
 // item per field), apply chunks.
-enum { L_BOX3F, L_BOX3D, L_BOX2F, L_BOX2D, L_FIN, L_APPLY, L_ORD, NLISTS };
+enum { L_BOX3F, L_BOX3D, L_BOX2F, L_BOX2D, L_FIN, L_APPLY, L_ORD, L_EVT, NLISTS };
 static size_t list_words(size_t nf) { return 2 + 2 * nf + 1; }
 
 namespace exz {
@@ -284,7 +268,8 @@ static void box_launch_check(int ty, int tz, const FieldDev *fields, const uint3
 // Issue `iters` batched iterations.
 static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dlists, size_t lw,
                              const BatchShape &shape, int iters, int grid_box,
-                             int grid_fin, int grid_apply, int grid_ord, hipStream_t s) {
+                             int grid_fin, int grid_apply, int grid_ord, int grid_evt,
+                             hipStream_t s) {
   const uint32_t item_quads = shape.item_quads;
   auto list = [&](int q) { return dlists + q * lw; };
   uint32_t *lf = list(L_FIN), *la = list(L_APPLY), *lo = list(L_ORD);
@@ -293,6 +278,9 @@ static void issue_iterations(exz_ctx *ctx, const FieldDev *fields, uint32_t *dli
     box_launch_check<double>(shape.ty3, shape.tz3, fields, list(L_BOX3D), ctx->d_conn, grid_box, s);
     box_launch_check<float>(shape.ty2, shape.tz2, fields, list(L_BOX2F), ctx->d_conn, grid_box, s);
     box_launch_check<double>(shape.ty2, shape.tz2, fields, list(L_BOX2D), ctx->d_conn, grid_box, s);
+    // original-mode members: their event constraints on the pointers the
+    // check just wrote
+    if (grid_evt > 0) (void)launch_events_batch(fields, list(L_EVT), ctx->d_comp, grid_evt, s);
     hipLaunchKernelGGL(k_order_batch, dim3(grid_ord), dim3(256), 0, s, fields, lo);
     hipLaunchKernelGGL(k_apply_batch, dim3(grid_apply), dim3(APPLY_BLOCK), 0, s, fields, la,
                        item_quads);
@@ -323,6 +311,10 @@ static void build_lists(const std::vector<const FieldDev *> &fds, const std::vec
     if (fd.mode != 1 && fd.K > 1) {
       f[L_ORD].push_back(idx);
       n[L_ORD].push_back(((uint32_t)fd.K - 1 + ORD_ITEM - 1) / ORD_ITEM);
+    }
+    if (fd.mode == 1 && fd.K > 0) {
+      f[L_EVT].push_back(idx);
+      n[L_EVT].push_back(((uint32_t)fd.K + EVENT_ITEM - 1) / EVENT_ITEM);
     }
   }
   for (int q = 0; q < NLISTS; ++q) {
@@ -361,15 +353,17 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
   HIP_OR_FAIL_B(hipHostMalloc((void **)&hstates, std::max<size_t>(nf, 1) * sizeof(State),
                               hipHostMallocDefault));
   // persistent grids: enough blocks to fill the chip, never more than items
-  uint64_t max_boxes = 0, max_apply = 0, max_ord = 0;
+  uint64_t max_boxes = 0, max_apply = 0, max_ord = 0, max_evt = 0;
   for (auto &m : members) {
     max_boxes += (uint64_t)m.fd.ntiles;
     max_apply += apply_items(m.fd, shape.item_quads);
     max_ord += ((uint64_t)m.fd.K + ORD_ITEM - 1) / ORD_ITEM;
+    if (m.fd.mode == 1) max_evt += ((uint64_t)m.fd.K + EVENT_ITEM - 1) / EVENT_ITEM;
   }
   const int grid_box = batch_grid(max_boxes, shape.grid_box, 8);
   const int grid_apply = batch_grid(max_apply, shape.grid_apply, 16);
   const int grid_ord = batch_grid(max_ord, 0, 8);
+  const int grid_evt = max_evt ? batch_grid(max_evt, 0, 8) : 0;
   int chunk = ctx->poll > 0 ? ctx->poll : 4;
   hipGraphExec_t exec = nullptr;
   int exec_chunk = 0;
@@ -395,7 +389,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
         hipGraph_t graph = nullptr;
         HIP_OR_FAIL_B(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_fin,
-                         grid_apply, grid_ord, s);
+                         grid_apply, grid_ord, grid_evt, s);
         const hipError_t ce = hipStreamEndCapture(s, &graph);  // always ends the capture
         HIP_OR_FAIL_B(ce);
         const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -406,7 +400,7 @@ exz_status run_batch_loop(exz_ctx *ctx, std::vector<Member> &members, FieldDev *
       HIP_OR_FAIL_B(hipGraphLaunch(exec, s));
     } else {
       issue_iterations(ctx, dev_fields, dlists, lw, shape, chunk, grid_box, grid_fin,
-                         grid_apply, grid_ord, s);
+                         grid_apply, grid_ord, grid_evt, s);
       HIP_OR_FAIL_B(hipGetLastError());
     }
     // the members' states are consecutive (one array, slot k = member k)
@@ -504,7 +498,6 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     results[k].certified = -1;
   }
   std::vector<Member> mem;
-  std::vector<int> singles;  // fields run through the single-field driver
   const BatchShape shape = batch_shape(ctx);
   for (int k = 0; k < nfields; ++k) {
     const exz_field &fl = fields[k];
@@ -518,10 +511,6 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
     if (m.status != EXZ_OK) {
       results[k].status = m.status;
       if (first_err == EXZ_OK) first_err = m.status;
-      continue;
-    }
-    if (fl.params.event_mode == EXZ_EVENT_ORIGINAL) {
-      singles.push_back(k);
       continue;
     }
     // box shape of the batch for this field's dimensionality
@@ -643,6 +632,37 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       }
       host_fd[k] = fd;
     }
+    // original-mode members: path workspace (f's and g's labels, saddle
+    // order, f's selections; the certificate's labels too) and its set-up,
+    // on the member's side stream after its critical points
+    Layout LP;
+    std::vector<size_t[6]> op(nb);
+    std::vector<size_t> baseP(nb, 0);
+    for (size_t k = 0; k < nb; ++k) {
+      if (!mem[k].active || mem[k].fd.mode != 1) continue;
+      Layout L;
+      layout_c(mem[k].fd, true, mem[k].certify, L, op[k]);
+      baseP[k] = LP.add(L.total);
+    }
+    if (LP.total) {
+      HIP_OR_FAIL_B(ctx->BC.reserve(LP.total));
+      char *Pm = (char *)ctx->BC.take(LP.total);
+      for (size_t k = 0; k < nb; ++k) {
+        Member &m = mem[k];
+        if (!m.active || m.fd.mode != 1) continue;
+        hipStream_t sk = ctx->side[k % exz_ctx::NSIDE];
+        FieldDev &fd = m.fd;
+        char *cb = Pm + baseP[k];
+        fd.lab_f = (uint32_t *)(cb + op[k][0]);
+        fd.lab = (uint32_t *)(cb + op[k][1]);
+        fd.sad_rank = (uint32_t *)(cb + op[k][2]);
+        fd.sel_f = (uint32_t *)(cb + op[k][3]);
+        HIP_OR_FAIL_B(launch_original_setup(fd, ctx->d_comp, (uint32_t *)(cb + op[k][4]),
+                                            (uint32_t *)(cb + op[k][5]),
+                                            scan_tmp_words((uint32_t)(fd.K ? fd.K : 1)), sk));
+        host_fd[k] = fd;
+      }
+    }
     HIP_OR_FAIL_B(side_join(ctx, s));
     HIP_OR_FAIL_B(hipMemcpyAsync(dev_fields, host_fd.data(), nb * sizeof(FieldDev),
                                  hipMemcpyHostToDevice, s));
@@ -664,8 +684,12 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       if (m.status != EXZ_OK || !m.certify) continue;
       uint32_t *lab_g = nullptr;
       FieldDev fd = m.fd;
-      const exz_status cs = setup_paths(ctx, fd, false, true, ctx->C, &lab_g, s);
-      if (cs != EXZ_OK) return cs;
+      if (fd.mode == 1) {
+        lab_g = fd.lab;  // its path workspace holds the certificate's labels
+      } else {
+        const exz_status cs = setup_paths(ctx, fd, false, true, ctx->C, &lab_g, s);
+        if (cs != EXZ_OK) return cs;
+      }
       HIP_OR_FAIL_B(launch_certify(fd, ctx->d_comp, lab_g, s));
       HIP_OR_FAIL_B(hipStreamSynchronize(s));
     }
@@ -698,14 +722,6 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       r.loop_ms = loop_ms;
     }
   }
-  ctx->busy = false;  // the single-field driver takes the context itself
-  for (int k : singles) {
-    const exz_field &fl = fields[k];
-    const exz_status st = exz_correct(ctx, fl.f, fl.g_hat, fl.g_out, fl.cnt_io, &fl.params,
-                                      &results[k], stream);
-    if (st < 0 && first_err == EXZ_OK) first_err = st;
-  }
-  ctx->busy = true;
   return first_err;
 }
 
@@ -962,7 +978,7 @@ exz_status exz_step(exz_ctx *ctx, exz_job *const *jobs, int32_t njobs, int32_t i
   const int grid_box = batch_grid(boxes, shape.grid_box, 8);
   const int grid_apply = batch_grid(words, shape.grid_apply, 16);
   const int grid_ord = batch_grid(ords, 0, 8);
-  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, (int)nf, grid_apply, grid_ord, s);
+  issue_iterations(ctx, df, dl, lw, shape, iters, grid_box, (int)nf, grid_apply, grid_ord, 0, s);
   HIP_OR_FAIL_B(hipGetLastError());
   // each job's state after the step, into the next of its host slots, for
   // exz_job_query (which reads the latest slot whose copy has ended)

@@ -122,7 +122,7 @@ struct exz_ctx {
   exz::State *h_state = nullptr;    // pinned
   uint32_t *h_k = nullptr;          // pinned
   exz::Arena A, B, C;
-  exz::Arena BA, BB;  // batched correction workspaces
+  exz::Arena BA, BB, BC;  // batched correction workspaces (per-vertex, per-CP, paths)
   void *step_host = nullptr;  // exz_step staging: pinned FieldDev array + item lists
   void *step_dev = nullptr;
   size_t step_cap = 0;

@@ -127,6 +127,24 @@ __device__ __forceinline__ __attribute__((address_space(1))) P *glob(P *p) {
 // Adds vertex t to the target set: a plain byte store (every writer stores
 // the same value, so concurrent marks of one target need no atomics; the
 // cache keeps per-byte dirty masks, so neighbouring marks do not clash).
+// Batched item lists ([nf, total, field[nf], base[nf + 1]]): the field slot
+// of item `it` (largest k with base[k] <= it), found by walking forward from
+// slot k: a block (or thread) visits its items in increasing order, so the
+// walk is short and reads a few cached words.
+__device__ __forceinline__ uint32_t next_field(const uint32_t *base, uint32_t nf, uint32_t it,
+                                               uint32_t k) {
+  while (k + 1 < nf && base[k + 1] <= it) ++k;
+  return k;
+}
+
+// The same for a whole work-group (it is the same on every lane): the slot
+// is made explicitly wave-uniform so the field's descriptor is read with
+// scalar loads.
+__device__ __forceinline__ uint32_t next_field_uniform(const uint32_t *base, uint32_t nf,
+                                                       uint32_t it, uint32_t k) {
+  return __builtin_amdgcn_readfirstlane(next_field(base, nf, it, k));
+}
+
 // Target marks carry the pass that made them: a mark is the pass's tag byte
 // (1 .. MARK_TAGS, in turn; 0 = none), so apply takes the bytes equal to the
 // current tag and need not clear them.  The apply of a pass with the last
@@ -289,6 +307,11 @@ hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, const uint
                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_finalize(const FieldDev &fd, hipStream_t s);
 hipError_t launch_certify(const FieldDev &fd, const uint8_t *comp, uint32_t *lab_g, hipStream_t s);
+// The original-mode event kernel over the original-mode fields of a batch:
+// item lists as the other batched passes, 256 critical points per item.
+constexpr uint32_t EVENT_ITEM = 256;
+hipError_t launch_events_batch(const FieldDev *fields, const uint32_t *lists, const uint8_t *comp,
+                               int grid, hipStream_t s);
 hipError_t launch_original_setup(const FieldDev &fd, const uint8_t *comp, uint32_t *tmp,
                                  uint32_t *scan_tmp, size_t scan_words, hipStream_t s);
 hipError_t launch_original_events(const FieldDev &fd, const uint8_t *comp, hipStream_t s);

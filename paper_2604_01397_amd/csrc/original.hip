@@ -219,11 +219,11 @@ __device__ __forceinline__ uint32_t select_extremum_g(const FieldDev &fd, const 
   return best;
 }
 
+// The event constraints of thread k: C2 for the k-th saddle in f's order,
+// C3 for the critical point in vertex-order slot k.
 template <class T>
-__global__ void k_events(FieldDev fd, const uint8_t *comp) {
+__device__ __forceinline__ void events_one(const FieldDev &fd, const uint8_t *comp, uint32_t k) {
   const State *st = fd.st;
-  if (st->done) return;
-  const uint32_t k = blockIdx.x * 256 + threadIdx.x;
   const uint32_t ns = st->nsaddle;
   const uint32_t tag = st->tag;
   const T *G = (const T *)fd.g;
@@ -257,6 +257,30 @@ __global__ void k_events(FieldDev fd, const uint8_t *comp) {
   if (Mf != NONE && gupper) {
     const uint32_t Mg = select_extremum_g(fd, G, fd.lab, s, gupper, false);
     if (Mg != Mf) mark_target(fd.tmark, Mf, tag);
+  }
+}
+
+template <class T>
+__global__ void k_events(FieldDev fd, const uint8_t *comp) {
+  if (fd.st->done) return;
+  events_one<T>(fd, comp, blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(EVENT_ITEM) k_events_batch(const FieldDev *__restrict__ fields,
+                                                             const uint32_t *__restrict__ lists,
+                                                             const uint8_t *comp) {
+  const uint32_t nf = lists[0], total = lists[1];
+  const uint32_t *field = lists + 2, *base = lists + 2 + nf;
+  uint32_t k = 0;
+  for (uint32_t it = blockIdx.x; it < total; it += gridDim.x) {
+    k = next_field_uniform(base, nf, it, k);
+    const FieldDev &fd = fields[__builtin_amdgcn_readfirstlane(field[k])];
+    if (fd.st->done) continue;
+    const uint32_t c = (it - base[k]) * EVENT_ITEM + threadIdx.x;
+    if (fd.dtype == 0)
+      events_one<float>(fd, comp, c);
+    else
+      events_one<double>(fd, comp, c);
   }
 }
 
@@ -349,6 +373,12 @@ hipError_t launch_original_events(const FieldDev &fd, const uint8_t *comp, hipSt
     hipLaunchKernelGGL(k_events<float>, dim3(gk), dim3(256), 0, s, fd, comp);
   else
     hipLaunchKernelGGL(k_events<double>, dim3(gk), dim3(256), 0, s, fd, comp);
+  return hipGetLastError();
+}
+
+hipError_t launch_events_batch(const FieldDev *fields, const uint32_t *lists, const uint8_t *comp,
+                               int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_events_batch, dim3(grid), dim3(EVENT_ITEM), 0, s, fields, lists, comp);
   return hipGetLastError();
 }
 

@@ -175,3 +175,33 @@ def test_batch_box_shapes_invariance(ctx):
         torch.cuda.synchronize()
         for c, a, b in zip(cases, ref, out):
             assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), (c.name, b3, b2)
+
+
+def test_batch_original_members_in_the_batched_loop(ctx):
+    """Original-mode members (Sec. 4.2) run in the batched launches with the
+    reformulated ones (their event kernel over per-field items, their path
+    workspace set up in the batch): each equals its plain original-mode
+    correction and the oracle's, certificates included, and the reformulated
+    members are unchanged."""
+    from paper_2604_01397_amd import exactz
+    cases = _mixed_cases()
+    items = []
+    for k, c in enumerate(cases):
+        mode = exactz.ORIGINAL if k % 2 == 0 else exactz.REFORMULATED
+        items.append({"f": _dev(c.f), "g_hat": _dev(c.g_hat), "xi": c.xi, "mode": mode,
+                      "certify": k % 3 == 0})
+    print("batch of", len(items), "with original-mode members", flush=True)
+    out = ctx.correct_batch(items)
+    torch.cuda.synchronize()
+    for c, it, (g_out, cnt, r) in zip(cases, items, out):
+        print("field", c.name, "mode", it["mode"], r["iterations"], r["status"], flush=True)
+        g1, c1, r1 = ctx.correct(it["f"], it["g_hat"], c.xi, mode=it["mode"],
+                                 certify=it["certify"])
+        torch.cuda.synchronize()
+        assert torch.equal(g_out, g1) and torch.equal(cnt, c1), c.name
+        for k in ("iterations", "edited_vertices", "edit_ops", "num_critical", "status",
+                  "certified"):
+            assert r[k] == r1[k], (c.name, k, r[k], r1[k])
+        go, co, st, _ = oracle.correct(c.f, c.g_hat, c.xi, mode=it["mode"])
+        assert np.array_equal(_bits(g_out.cpu().numpy()), _bits(go)), c.name
+        assert np.array_equal(cnt.cpu().numpy(), co), c.name
