@@ -430,7 +430,7 @@ def main():
                    "status": res["status"], "status_text": STATUS_TEXT.get(res["status"], "?"),
                    "residual_violations": res["residual_violations"],
                    "targets_total": res["targets_total"]},
-        "roofline": {"bound": "hbm", "kernel": "k_check", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_check (with the order test)", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_over_algorithmic": (round(traffic / algo_bytes, 3)
