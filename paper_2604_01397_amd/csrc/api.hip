@@ -208,8 +208,8 @@ void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, La
   off[5] = L.add(n);                                         // fe
   off[6] = own_cnt ? L.add(n) : 0;                           // cnt
   off[7] = L.add(4 * scan_tmp_words((uint32_t)fd.nchunk));   // scan tmp
-  // dirty box flags, sized for the smallest box (64 x 1 x 1) so the
-  // footprint does not depend on the box shape
+  // dirty box flags and their list, sized for the smallest box (64 x 1 x 1)
+  // so the footprint does not depend on the box shape
   off[8] = L.add(box_flag_bytes(fd));
   (void)trace_cap;
   (void)need_lab;
@@ -254,8 +254,10 @@ exz_status setup_phase_a(exz_ctx *ctx, FieldDev &fd, const void *f, const void *
   fd.cpbits = (unsigned long long *)(base + oa[2]);
   fd.cpoff = (uint32_t *)(base + oa[3]);
   fd.tmark = (uint8_t *)(base + oa[4]);
+  fd.mchunk = fd.tmark + mark_pad_bytes(fd);
   fd.fe = (uint8_t *)(base + oa[5]);
   fd.bdirty = (uint8_t *)(base + oa[8]);
+  fd.blist = box_list_of(fd, base + oa[8]);
   fd.cnt = cnt_io ? cnt_io : (uint8_t *)(base + oa[6]);
   fd.vec = quad_aligned(fd);
   uint32_t *scan_tmp = (uint32_t *)(base + oa[7]);
@@ -291,8 +293,7 @@ exz_status setup_phase_b(exz_ctx *ctx, FieldDev &fd, uint32_t K, Arena &B, hipSt
   uint32_t *stmp = (uint32_t *)(bb + ob[10]);
   const size_t hw = radix_hist_words(K ? K : 1);
   if (K > 0) {
-    HIP_OR_FAIL(launch_cp_compact(fd, ctx->d_comp, keys, s));
-    HIP_OR_FAIL(launch_iota(vals, K, s));
+    HIP_OR_FAIL(launch_cp_compact(fd, ctx->d_comp, keys, vals, s));
     HIP_OR_FAIL(launch_radix_sort(fd.dtype == 0 ? 4 : 8, keys, vals, keys_tmp, vals_tmp, K, hist,
                                   stmp, scan_tmp_words((uint32_t)(hw - 1)), s));
     HIP_OR_FAIL(launch_cp_init(fd, vals, s));
@@ -662,6 +663,7 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
                    C, &lab_g, s);
   if (st != EXZ_OK) return st;
   HIP_OR_FAIL(hipEventRecord(ctx->ev_setup, s));
+  fd.chunk_marks = 1;  // the iterations below run the single-field kernels
 
   // Iterations are issued in chunks; each chunk ends with an asynchronous
   // copy of the device state into one of two pinned slots.  The host keeps

@@ -560,8 +560,10 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.cpbits = (unsigned long long *)(b + oa[k][2]);
       fd.cpoff = (uint32_t *)(b + oa[k][3]);
       fd.tmark = (uint8_t *)(b + oa[k][4]);
+      fd.mchunk = fd.tmark + mark_pad_bytes(fd);
       fd.fe = (uint8_t *)(b + oa[k][5]);
       fd.bdirty = (uint8_t *)(b + oa[k][8]);
+      fd.blist = box_list_of(fd, b + oa[k][8]);
       uint8_t *cnt_io = fields[mem[k].index].cnt_io;
       fd.cnt = cnt_io ? cnt_io : (uint8_t *)(b + oa[k][6]);
       fd.vec = quad_aligned(fd);
@@ -622,8 +624,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.cpr = b + ob[k][4];
       if (K > 0) {
         const size_t hw = radix_hist_words(K);
-        HIP_OR_FAIL_B(launch_cp_compact(fd, ctx->d_comp, b + ob[k][5], sk));
-        HIP_OR_FAIL_B(launch_iota((uint32_t *)(b + ob[k][7]), K, sk));
+        HIP_OR_FAIL_B(launch_cp_compact(fd, ctx->d_comp, b + ob[k][5], (uint32_t *)(b + ob[k][7]), sk));
         HIP_OR_FAIL_B(launch_radix_sort(fd.dtype == 0 ? 4 : 8, b + ob[k][5], (uint32_t *)(b + ob[k][7]),
                                         b + ob[k][6], (uint32_t *)(b + ob[k][8]), K,
                                         (uint32_t *)(b + ob[k][9]), (uint32_t *)(b + ob[k][10]),

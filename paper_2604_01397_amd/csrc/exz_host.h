@@ -82,17 +82,27 @@ inline int quad_aligned(const FieldDev &fd) {
 
 // Bytes of the target marks: one per vertex, then zero padding (apply reads
 // marks four at a time), rounded to 16.
-inline size_t mark_bytes(const exz::FieldDev &fd) { return ((size_t)fd.n + 64 + 15) / 16 * 16; }
+inline size_t mark_pad_bytes(const exz::FieldDev &fd) { return ((size_t)fd.n + 64 + 15) / 16 * 16; }
+// The marks (zero padded) and the tags of their 256-vertex chunks.
+inline size_t mark_bytes(const exz::FieldDev &fd) {
+  return mark_pad_bytes(fd) + ((size_t)fd.n + 255) / 256;
+}
 
 // Bytes of the dirty-box flags: one per box of the smallest shape.
-inline size_t box_flag_bytes(const exz::FieldDev &fd) {
+inline size_t box_flag_count(const exz::FieldDev &fd) {
   return (size_t)fd.tiles_x * (size_t)fd.ny * (size_t)fd.nz;
+}
+// The flags (padded to 16 bytes) followed by the box list.
+inline size_t box_flag_bytes(const exz::FieldDev &fd) {
+  return (box_flag_count(fd) + 15) / 16 * 16 + 4 * box_flag_count(fd);
+}
+inline uint32_t *box_list_of(const exz::FieldDev &fd, char *flags) {
+  return (uint32_t *)(flags + (box_flag_count(fd) + 15) / 16 * 16);
 }
 
 void layout_a(const FieldDev &fd, bool own_cnt, int trace_cap, bool need_lab, Layout &L,
               size_t off[9]);
 void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]);
-hipError_t launch_iota(uint32_t *v, uint32_t n, hipStream_t s);
 // 32-bit words of the pointer-jumping convergence bitmask of count labels.
 size_t jump_conv_words(uint64_t count);
 void layout_c(const FieldDev &fd, bool original, bool certify, Layout &L, size_t off[6]);

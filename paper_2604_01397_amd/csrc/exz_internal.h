@@ -51,6 +51,7 @@ struct State {
   int32_t busy;           // the last apply changed many values (> n / 64): the next apply
                           // fetches every quad's counts ahead
   uint32_t tag;           // mark byte of this pass's targets (1 .. MARK_TAGS)
+  uint32_t nfront;        // boxes in the frontier list (single-field loop)
   uint32_t jump[MAX_JUMP_ROUNDS];  // pointer-jumping round flags
   int64_t iterations;
   int64_t edit_ops;
@@ -81,6 +82,7 @@ struct FieldDev {
   int32_t grid_blocks;       // stencil grid: 0 one block per box, < 0 persistent default, > 0 fixed
   int32_t trace_cap;
   int32_t frontier;     // 1: re-check only boxes whose closed neighbourhood changed
+  int32_t chunk_marks;  // 1 (single-field loop): frontier passes tag the chunks they mark
   int32_t ty_shift, tz_shift;  // log2 of tile_y / tile_z
   int32_t vec;          // f, g 16-byte and cnt 4-byte aligned: apply reads four vertices at once
   int32_t dlt[16];      // linear index offset of each slot (dlt[SELF] = 0)
@@ -107,7 +109,11 @@ struct FieldDev {
   uint32_t *lab;        // 2n: g's descent / ascent labels (original mode)
   uint32_t *lab_f;      // 2n: f's resolved path termini (original mode, certificate)
   uint8_t *tmark;       // n: the target set of the iteration (1 = decrease this vertex)
+  uint8_t *mchunk;      // n / 256: the tag of the last pass that marked a vertex of the
+                        // 256-vertex chunk (apply passes over chunks without marks)
   uint8_t *bdirty;      // ntiles: boxes whose check reads a value the last apply changed
+  uint32_t *blist;      // ntiles: the flagged boxes, listed (and their flags cleared) after
+                        // each single-field apply for the next frontier check
   int64_t *trace;       // 2 * trace_cap (|S|, changed) per iteration, nullable
   State *st;
 };
@@ -148,10 +154,21 @@ __device__ __forceinline__ uint32_t next_field_uniform(const uint32_t *base, uin
 // Target marks carry the pass that made them: a mark is the pass's tag byte
 // (1 .. MARK_TAGS, in turn; 0 = none), so apply takes the bytes equal to the
 // current tag and need not clear them.  The apply of a pass with the last
-// tag zeroes the whole array, so no mark outlives the cycle of tags.
+// tag zeroes the whole array, so no mark outlives the cycle of tags.  The
+// 256-vertex chunk of a mark gets the tag too; a chunk tag left over from an
+// earlier cycle only makes apply visit a chunk without marks.
+// Chunks are tagged (CH) only in the frontier passes of the single-field
+// loop, which mark few vertices; the apply after such a pass skips untagged
+// chunks.
 constexpr uint32_t MARK_TAGS = 254;
-__device__ __forceinline__ void mark_target(uint8_t *marks, uint32_t t, uint32_t tag) {
-  glob(marks)[t] = (uint8_t)tag;
+constexpr uint32_t MARK_CHUNK_SHIFT = 8;
+__device__ __forceinline__ bool chunk_pass(const FieldDev &fd) {
+  return fd.chunk_marks && fd.frontier && !fd.st->dense;
+}
+template <bool CH = false>
+__device__ __forceinline__ void mark_target(const FieldDev &fd, uint32_t t, uint32_t tag) {
+  glob(fd.tmark)[t] = (uint8_t)tag;
+  if (CH) glob(fd.mchunk)[t >> MARK_CHUNK_SHIFT] = (uint8_t)tag;
 }
 
 // Simulation of Simplicity: (a, ia) < (b, ib).  Bitwise, not short-circuit,
@@ -295,7 +312,8 @@ hipError_t launch_setup(const FieldDev &fd, const uint32_t *conn, hipStream_t s)
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, uint32_t count, uint32_t *tmp,
                            size_t tmp_words, hipStream_t s);
 size_t scan_tmp_words(uint32_t count);
-hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *comp, void *keys, hipStream_t s);
+hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *comp, void *keys, uint32_t *vals,
+                             hipStream_t s);
 hipError_t launch_radix_sort(int key_bytes, void *keys, uint32_t *vals, void *keys_tmp,
                              uint32_t *vals_tmp, uint32_t count, uint32_t *hist, uint32_t *scan_tmp,
                              size_t scan_words, hipStream_t s);

@@ -23,11 +23,12 @@
 // each thread evaluates TZ vertices of one (x, y) column from LDS.  Halo
 // re-reads are served by L2: consecutive boxes run on the same XCD.  With
 // frontier passes, apply flags the boxes whose check reads a value it
-// changed: the boxes around the vertex, and the box of the previous critical
-// point in f's order, which compares itself with the vertex.  The next check
-// visits only flagged boxes; a pass that changes nothing is followed by one
-// dense pass before the loop may stop, so the decision always rests on a
-// check of every vertex.
+// changed (the boxes around the vertex), finalize lists the flagged boxes,
+// and the next check visits only those, spread evenly over its work-groups
+// (the flagged boxes cluster where the field still moves, so a fixed share
+// of the boxes per work-group would leave most of them idle); a pass that
+// changes nothing is followed by one dense pass before the loop may stop, so
+// the decision always rests on a check of every vertex.
 #include <algorithm>
 
 #include "loop_box.h"
@@ -61,7 +62,6 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   State *st = fd.st;
   if (st->done) return;
   __shared__ CheckLds<T, TY, TZ> L;
-  __shared__ unsigned long long pick;
   load_conn(L, conn);
   const BoxWalk w = box_walk(fd);
   const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
@@ -75,15 +75,12 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   const uint32_t K = (uint32_t)fd.K, tag = st->tag;
   const uint32_t tid = threadIdx.y * 64 + threadIdx.x, per = 4u * 64u * TY;
   uint32_t ob = blockIdx.x * per;  // this work-group's next item
-  if (!fd.frontier || st->dense) {
-    // a dense pass consumes every box flag: clear them, so none is stale
+  const bool dense = !fd.frontier || st->dense;
+  if (dense) {
     for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
       const BoxOrigin o = box_of(fd, tile, TY, TZ);
       check_box<T, TY, TZ>(fd, o, L);
-      if (lead) {
-        done_v += box_vertices(fd, o, TY, TZ);
-        if (fd.frontier) fd.bdirty[tile] = 0;
-      }
+      if (lead) done_v += box_vertices(fd, o, TY, TZ);
       __syncthreads();
       if (order && ob + 1 < K) {
         order_quad<T>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
@@ -93,36 +90,30 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   } else {
     // Frontier pass: a box none of whose cells (halo included) changed in
     // the last apply would name the same targets as at its last check, and
-    // those were all blocked then and still are, so only dirty boxes are
-    // checked.  The first wave reads (and clears) the flags of the block's
-    // next 64 boxes.
-    for (uint32_t t0 = w.first; t0 < w.end; t0 += 64u * w.stride) {
-      if (threadIdx.y == 0) {
-        const uint32_t tile = t0 + threadIdx.x * w.stride;
-        bool d = false;
-        if (tile < w.end) {
-          d = fd.bdirty[tile] != 0;
-          if (d) fd.bdirty[tile] = 0;
-        }
-        const unsigned long long b = __ballot(d);
-        if (threadIdx.x == 0) pick = b;
-      }
+    // those were all blocked then and still are, so only the listed (dirty)
+    // boxes are checked.  XCD x takes the x-th eighth of the list and its
+    // work-groups interleave over it, so every work-group checks the same
+    // number of boxes (to one) and boxes adjacent in the list, which are
+    // near in the field, share an L2.
+    const uint32_t M = st->nfront, G = gridDim.x, x = blockIdx.x & 7u;
+    const uint32_t nx = G < 8 ? G : 8;
+    const uint32_t lo = (uint32_t)((unsigned long long)M * x / nx);
+    const uint32_t hi = (uint32_t)((unsigned long long)M * (x + 1) / nx);
+    const uint32_t mine = (G - x + 7) / 8;
+    for (uint32_t j = lo + (blockIdx.x >> 3); j < hi; j += mine) {
+      const BoxOrigin o = box_of(fd, glob(fd.blist)[j], TY, TZ);
+      check_box<T, TY, TZ, true>(fd, o, L);
+      if (lead) done_v += box_vertices(fd, o, TY, TZ);
       __syncthreads();
-      unsigned long long b = pick;
-      __syncthreads();  // pick is rewritten for the next 64 boxes
-      while (b) {
-        const uint32_t k = (uint32_t)(__ffsll(b) - 1);
-        b &= b - 1;
-        const BoxOrigin o = box_of(fd, t0 + k * w.stride, TY, TZ);
-        check_box<T, TY, TZ>(fd, o, L);
-        if (lead) done_v += box_vertices(fd, o, TY, TZ);
-        __syncthreads();
-      }
     }
   }
   if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
-  if (order)
+  // (a frontier pass tags the chunks of its marks, for the apply after it)
+  if (order && dense)
     for (; ob + 1 < K; ob += gridDim.x * per) order_quad<T>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
+  else if (order)
+    for (; ob + 1 < K; ob += gridDim.x * per)
+      order_quad<T, true>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
 }
 
 // Reference topology of f, box by box over the same persistent walk.
@@ -141,13 +132,74 @@ __global__ void __launch_bounds__(64 * TY) k_ref(FieldDev fd, const uint32_t *__
 template <class T>
 __global__ void __launch_bounds__(APPLY_BLOCK) k_apply(FieldDev fd) {
   if (fd.st->done) return;
+  // the list of the last frontier check has been read: finalize refills it
+  if (blockIdx.x == 0 && threadIdx.x == 0) fd.st->nfront = 0;
   const uint32_t nq = ((uint32_t)fd.n + 3) / 4;
   EditCount ec = {{0, 0, 0, 0, 0}};
-  apply_quads<T>(fd, blockIdx.x * APPLY_BLOCK + threadIdx.x, gridDim.x * APPLY_BLOCK, nq, ec);
+  apply_quads<T, true>(fd, blockIdx.x * APPLY_BLOCK + threadIdx.x, gridDim.x * APPLY_BLOCK, nq, ec);
   flush_counts<APPLY_BLOCK / 64>(fd.st, ec, blockIdx.x);
 }
 
-__global__ void __launch_bounds__(64) k_finalize(FieldDev fd) { finalize_field(fd); }
+// Frontier list: work-group b >= 1 of finalize takes LIST_TILES box flags,
+// 16 per thread, lists the flagged boxes (block-wide prefix sum, one atomic
+// per work-group for its place in the list) and clears their flags.  The
+// list's order does not matter to the check; each work-group's part of it is
+// in box order.
+constexpr int LIST_BLOCK = 256;
+constexpr uint32_t LIST_TILES = 16u * LIST_BLOCK;
+
+__device__ __forceinline__ void list_dirty_boxes(const FieldDev &fd, uint32_t part) {
+  __shared__ uint32_t wsum[LIST_BLOCK / 64];
+  __shared__ uint32_t base;
+  const uint32_t nt = (uint32_t)fd.ntiles, tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t t0 = part * LIST_TILES + 16u * tid;
+  uint8_t *F = fd.bdirty;
+  uint32_t bits = 0;  // bit k: box t0 + k is flagged
+  const bool whole = t0 + 16 <= nt;  // 16-byte aligned: the flags start 256-aligned
+  if (whole) {
+    const u32x4 v = *glob(reinterpret_cast<const u32x4 *>(F + t0));
+    const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int c = 0; c < 16; ++c) bits |= (((wd[c >> 2] >> (8 * (c & 3))) & 255u) != 0) << c;
+  } else {
+    for (uint32_t c = 0; t0 + c < nt && c < 16; ++c) bits |= (uint32_t)(glob(F)[t0 + c] != 0) << c;
+  }
+  const uint32_t cnt = (uint32_t)__popc(bits);
+  uint32_t incl = cnt;  // inclusive prefix over the wave
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d);
+    if (lane >= (uint32_t)d) incl += o;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t woff = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < LIST_BLOCK / 64; ++k) {
+    woff += (uint32_t)k < w ? wsum[k] : 0u;
+    total += wsum[k];
+  }
+  if (tid == 0) base = total ? atomicAdd(&fd.st->nfront, total) : 0u;
+  __syncthreads();
+  if (!bits) return;
+  uint32_t pos = base + woff + incl - cnt;
+  for (uint32_t b = bits; b; b &= b - 1) glob(fd.blist)[pos++] = t0 + (uint32_t)(__ffs(b) - 1);
+  if (whole)
+    *glob(reinterpret_cast<u32x4 *>(F + t0)) = u32x4{0u, 0u, 0u, 0u};
+  else
+    for (uint32_t b = bits; b; b &= b - 1) glob(F)[t0 + (uint32_t)(__ffs(b) - 1)] = 0;
+}
+
+// Work-group 0: the loop decision; the others (frontier passes only): the
+// frontier list of the boxes the apply just flagged.
+__global__ void __launch_bounds__(LIST_BLOCK) k_finalize(FieldDev fd) {
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 64) finalize_field(fd);
+    return;
+  }
+  if (fd.st->done) return;  // (set by work-group 0 meanwhile: the list goes unused)
+  list_dirty_boxes(fd, blockIdx.x - 1);
+}
 
 __global__ void __launch_bounds__(64) k_state_reset(State *st, int64_t max_iters) {
   const int lane = threadIdx.x;
@@ -163,6 +215,7 @@ __global__ void __launch_bounds__(64) k_state_reset(State *st, int64_t max_iters
   st->noflag = 1;  // the first iterations change values in nearly every box
   st->busy = 1;
   st->tag = 1;
+  st->nfront = 0;
   st->iterations = st->edit_ops = st->lossless_total = st->floor_total = st->edited_total = 0;
   st->targets_total = 0;
   st->residual = 0;
@@ -236,7 +289,8 @@ static void launch_phases(const FieldDev &fd, const uint32_t *conn, const uint8_
                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   launch_check_events<T>(fd, conn, comp, s, ev0, ev1);
   launch_apply<T>(fd, s);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, fd);
+  const uint32_t lists = fd.frontier ? ((uint32_t)fd.ntiles + LIST_TILES - 1) / LIST_TILES : 0u;
+  hipLaunchKernelGGL(k_finalize, dim3(1 + lists), dim3(LIST_BLOCK), 0, s, fd);
 }
 
 hipError_t launch_iteration(const FieldDev &fd, const uint32_t *conn, const uint8_t *comp,

@@ -233,14 +233,15 @@ __device__ __forceinline__ uint32_t box_vertices(const FieldDev &fd, BoxOrigin o
 
 // Adds the targets named by vertex i's request mask r (bit s: the neighbour
 // in slot s, at offset dlt[s]; bit SELF: i itself).
+template <bool CH>
 __device__ __forceinline__ void post_targets(const FieldDev &fd, const int32_t *dlt, uint32_t i,
                                              uint32_t r, uint32_t tag) {
-  if ((r >> SELF) & 1u) mark_target(fd.tmark, i, tag);
+  if ((r >> SELF) & 1u) mark_target<CH>(fd, i, tag);
   r &= LOW_MASK;
   while (r) {
     const int s = __ffs(r) - 1;
     r &= r - 1;
-    mark_target(fd.tmark, (uint32_t)((int)i + dlt[s]), tag);
+    mark_target<CH>(fd, (uint32_t)((int)i + dlt[s]), tag);
   }
 }
 
@@ -436,7 +437,7 @@ struct PlaneKeys {
 // the squares are kept, so the steepest neighbours cost 9 max and 9 min
 // operations per vertex.  Requests and, in original mode, g's pointers are
 // those of check_vertex.
-template <int TY, int TZ>
+template <int TY, int TZ, bool CH>
 __device__ __forceinline__ void check_column_keys(const FieldDev &fd, CheckLds<float, TY, TZ> &L,
                                                   BoxOrigin o, const uint32_t *refs, bool interior,
                                                   uint32_t tag) {
@@ -497,7 +498,7 @@ __device__ __forceinline__ void check_column_keys(const FieldDev &fd, CheckLds<f
     if (col && z < fd.nz) {
       const uint32_t i = i0 + (uint32_t)k * plane;
       const uint32_t r = requests_of(L.conn, vm, asc, desc, lower, refs[k] & 255u, refs[k] >> 8);
-      if (r) post_targets(fd, L.dlt, i, r, tag);
+      if (r) post_targets<CH>(fd, L.dlt, i, r, tag);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
         glob(fd.lab)[i] = (uint32_t)((int)i + L.dlt[desc]);
         glob(fd.lab)[fd.n + i] = (uint32_t)fd.n + (uint32_t)((int)i + L.dlt[asc]);
@@ -520,7 +521,7 @@ __device__ __forceinline__ void check_column_keys(const FieldDev &fd, CheckLds<f
 }
 
 // The plain (double field) check of one box's columns, vertex by vertex.
-template <int TY, int TZ>
+template <int TY, int TZ, bool CH>
 __device__ __forceinline__ void check_column_plain(const FieldDev &fd, CheckLds<double, TY, TZ> &L,
                                                    BoxOrigin o, bool interior, uint32_t tag) {
   using B = Box<TY, TZ>;
@@ -540,7 +541,7 @@ __device__ __forceinline__ void check_column_plain(const FieldDev &fd, CheckLds<
       uint32_t av = 0, dv = 0;
       const uint32_t r = check_vertex<double>(fd, L.conn, L.dlt, c, -B::PLANE, B::PLANE, x, y, z, i,
                                               rf & 255u, rf >> 8, av, dv, interior);
-      if (r) post_targets(fd, L.dlt, i, r, tag);
+      if (r) post_targets<CH>(fd, L.dlt, i, r, tag);
       if (fd.mode == 1) {  // original event constraints trace g's integral paths
         glob(fd.lab)[i] = dv;
         glob(fd.lab)[fd.n + i] = (uint32_t)fd.n + av;
@@ -554,7 +555,7 @@ __device__ __forceinline__ void check_column_plain(const FieldDev &fd, CheckLds<
 // original mode, write g's descent / ascent pointers).  The order of the
 // critical points of f (Sec. 4.3) is tested by its own pass (order_quad).
 // The caller synchronises the block after it.
-template <class T, int TY, int TZ>
+template <class T, int TY, int TZ, bool CH = false>
 __device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, CheckLds<T, TY, TZ> &L) {
   constexpr bool keyed = sizeof(T) == 4;  // float fields: tie-free keys
   const uint32_t tag = __builtin_amdgcn_readfirstlane(fd.st->tag);
@@ -581,13 +582,13 @@ __device__ __forceinline__ void check_box(const FieldDev &fd, BoxOrigin o, Check
   if constexpr (keyed) {
     stage_rows<TY, TZ, float, TagKey, double>(fd, (const float *)fd.g, L.S, o);
     __syncthreads();
-    check_column_keys<TY, TZ>(fd, L, o, refs, interior, tag);
+    check_column_keys<TY, TZ, CH>(fd, L, o, refs, interior, tag);
   } else {
     stage_rows<TY, TZ, double, AsIs, double>(fd, (const double *)fd.g, L.S, o);
 #pragma unroll
     for (int k = 0; k < TZ; ++k) L.ref[k][tid] = refs[k];
     __syncthreads();
-    check_column_plain<TY, TZ>(fd, L, o, interior, tag);
+    check_column_plain<TY, TZ, CH>(fd, L, o, interior, tag);
   }
 }
 
@@ -632,7 +633,7 @@ template <> struct Vec4<double> {
 // point's index is the lower one.  Every lane of the wave calls this (the
 // shuffle); lanes with r >= K test nothing.  K may cut the ranks short of
 // the field's count (a batched item stops there).
-template <class T>
+template <class T, bool CH = false>
 __device__ __forceinline__ void order_quad(const FieldDev &fd, uint32_t r, uint32_t K,
                                            bool next_in_lane, uint32_t tag) {
   const T *V = (const T *)fd.cpr;
@@ -651,7 +652,7 @@ __device__ __forceinline__ void order_quad(const FieldDev &fd, uint32_t r, uint3
     const T lo = a[c], hi = c < 3 ? a[c + 1] : nx;
     const bool below = (bw >> c) & 1u;
     if (r + c + 1 < K && (hi < lo || (hi == lo && below)))
-      mark_target(fd.tmark, glob(fd.cp_idx)[r + c], tag);
+      mark_target<CH>(fd, glob(fd.cp_idx)[r + c], tag);
   }
 }
 
@@ -883,25 +884,59 @@ __device__ __forceinline__ void mark_moved_boxes(const FieldDev &fd, uint32_t v,
 // in flight, high.  Box flags for the next frontier pass are set unless the
 // last pass changed so many values that the next check covers every box
 // anyway (State::noflag).
+//
+// With SKIP (a wave's lanes hold 64 consecutive quads from a multiple of 64,
+// and stride is a multiple of 64), after a frontier check that changed few
+// values, only the 256-vertex chunks tagged by this pass are visited: each
+// lane reads the chunk tag of one of the wave's steps, and the wave walks the
+// steps whose tag matches.
 template <class T>
+__device__ __forceinline__ void apply_quad(const FieldDev &fd, uint32_t q, QuadHead h, uint32_t tag,
+                                           bool wipe, bool flag, EditCount &ec) {
+  uint32_t moved = 0;
+  h.m = marks_of(h.m, tag);
+  if (wipe) *glob(reinterpret_cast<uint32_t *>(fd.tmark + 4u * q)) = 0;
+  if (h.m) {
+    QuadIn<T> d;
+    load_quad<T>(fd, 4u * q, h, d);
+    moved = edit_quad<T>(fd, 4u * q, h.m, d, ec);
+  }
+  if (flag) mark_moved_boxes(fd, 4u * q, moved);
+}
+
+template <class T, bool SKIP = false>
 __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uint32_t stride,
                                             uint32_t nq, EditCount &ec) {
   const bool flag = fd.frontier && !fd.st->noflag;
   const bool busy = fd.st->busy != 0;
   const uint32_t tag = fd.st->tag;
   const bool wipe = tag == MARK_TAGS;  // the last tag of the cycle: zero every mark
+  if (SKIP && !busy && !wipe && chunk_pass(fd)) {
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane(q0 >> 6), cs = stride >> 6;
+    const uint32_t nc = (nq + 63) >> 6, lane = __lane_id();
+    for (uint32_t s0 = 0; c0 + s0 * cs < nc; s0 += 64) {
+      const uint32_t c = c0 + (s0 + lane) * cs;
+      unsigned long long live = __ballot(c < nc && glob(fd.mchunk)[c] == tag);
+      if (!live) continue;
+      uint32_t q = q0 + (s0 + (uint32_t)(__ffsll(live) - 1)) * stride;
+      live &= live - 1;
+      QuadHead h = quad_head(fd, q, nq, busy);
+      for (;;) {
+        const uint32_t qn = live ? q0 + (s0 + (uint32_t)(__ffsll(live) - 1)) * stride : nq;
+        live &= live - 1;
+        const QuadHead hn = quad_head(fd, qn, nq, busy);
+        apply_quad<T>(fd, q, h, tag, false, flag, ec);
+        if (qn >= nq) break;
+        q = qn;
+        h = hn;
+      }
+    }
+    return;
+  }
   QuadHead h = quad_head(fd, q0, nq, busy);
   for (uint32_t q = q0; q < nq; q += stride) {
     const QuadHead hn = quad_head(fd, q + stride, nq, busy);
-    uint32_t moved = 0;
-    h.m = marks_of(h.m, tag);
-    if (wipe) *glob(reinterpret_cast<uint32_t *>(fd.tmark + 4u * q)) = 0;
-    if (h.m) {
-      QuadIn<T> d;
-      load_quad<T>(fd, 4u * q, h, d);
-      moved = edit_quad<T>(fd, 4u * q, h.m, d, ec);
-    }
-    if (flag) mark_moved_boxes(fd, 4u * q, moved);
+    apply_quad<T>(fd, q, h, tag, wipe, flag, ec);
     h = hn;
   }
 }

@@ -231,7 +231,7 @@ __device__ __forceinline__ void events_one(const FieldDev &fd, const uint8_t *co
   if (k + 1 < ns) {
     const uint32_t s = fd.cp_idx[fd.sad_rank[k]];
     const uint32_t sn = fd.cp_idx[fd.sad_rank[k + 1]];
-    if (sos_lt(G[sn], sn, G[s], s)) mark_target(fd.tmark, s, tag);
+    if (sos_lt(G[sn], sn, G[s], s)) mark_target(fd, s, tag);
   }
   // C3: selected extrema along the integral paths of g (thread k takes the
   // critical point in vertex-order slot k)
@@ -251,12 +251,12 @@ __device__ __forceinline__ void events_one(const FieldDev &fd, const uint8_t *co
   }
   if (mf != NONE && glower) {
     const uint32_t mg = select_extremum_g(fd, G, fd.lab, s, glower, true);
-    if (mg != mf) mark_target(fd.tmark, mg, tag);
+    if (mg != mf) mark_target(fd, mg, tag);
   }
   const uint32_t gupper = vm & ~glower;
   if (Mf != NONE && gupper) {
     const uint32_t Mg = select_extremum_g(fd, G, fd.lab, s, gupper, false);
-    if (Mg != Mf) mark_target(fd.tmark, Mf, tag);
+    if (Mg != Mf) mark_target(fd, Mf, tag);
   }
 }
 

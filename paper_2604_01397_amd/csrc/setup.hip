@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd) {
     if (!fd.resume) fd.cnt[i] = 0;
   }
   if (active) fd.tmark[i] = 0;
+  if (active && (i & 255u) == 0) fd.mchunk[i >> MARK_CHUNK_SHIFT] = 0;
   if (i < 64) fd.tmark[(uint32_t)fd.n + i] = 0;  // padding
   if (i < (uint32_t)fd.ntiles) fd.bdirty[i] = 0;  // ntiles <= n
   // one 64-bit word of the CP bitmask per wave (waves cover aligned chunks)
@@ -240,23 +241,28 @@ __device__ __forceinline__ unsigned long long sort_key(double v) {
   return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
 }
 
+// The critical points in vertex order (slot vo): their vertex, and the sort
+// key of f with the slot as payload.
 template <class T>
-__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_compact(FieldDev fd, void *keys_) {
+__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_compact(FieldDev fd, void *keys_,
+                                                            uint32_t *vals) {
   const uint32_t i = blockIdx.x * SETUP_BLOCK + threadIdx.x;
   if (i >= (uint32_t)fd.n || !is_cp(fd.cpbits, i)) return;
   const T *F = (const T *)fd.f;
   const uint32_t vo = cp_order(fd.cpbits, fd.cpoff, i);
   fd.cp_vtx[vo] = i;
+  vals[vo] = vo;
   using K = decltype(sort_key(T(0)));
   ((K *)keys_)[vo] = sort_key(F[i]);
 }
 
-hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *, void *keys, hipStream_t s) {
+hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *, void *keys, uint32_t *vals,
+                             hipStream_t s) {
   const int grid = (fd.n + SETUP_BLOCK - 1) / SETUP_BLOCK;
   if (fd.dtype == 0)
-    hipLaunchKernelGGL(k_cp_compact<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, keys);
+    hipLaunchKernelGGL(k_cp_compact<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, keys, vals);
   else
-    hipLaunchKernelGGL(k_cp_compact<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, keys);
+    hipLaunchKernelGGL(k_cp_compact<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, keys, vals);
   return hipGetLastError();
 }
 
@@ -316,21 +322,6 @@ hipError_t launch_debug_bounds(int dtype, const void *f, int64_t n, double xiT, 
   else
     hipLaunchKernelGGL(k_debug_bounds<double>, dim3(grid), dim3(256), 0, s, (const double *)f, n,
                        xiT, (double *)L, (double *)U);
-  return hipGetLastError();
-}
-
-}  // namespace exz
-
-namespace exz {
-
-__global__ void k_iota(uint32_t *v, uint32_t n) {
-  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) v[i] = i;
-}
-
-hipError_t launch_iota(uint32_t *v, uint32_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_iota, dim3((n + 255) / 256), dim3(256), 0, s, v, n);
   return hipGetLastError();
 }
 

@@ -238,6 +238,35 @@ def test_n_steps_bit_exact(ctx, n_steps):
     _compare(ctx, d.f, d.g_hat, d.xi, d.name, n_steps=n_steps)
 
 
+def _ramp_cascade(shape, rows):
+    """A slow ramp f = -0.2 x - 0.01 y - 0.001 z and g_hat = f except that, in
+    the given (y, z) rows, vertex x = 1 is put just below vertex x = 2.  Each
+    iteration then moves one vertex of such a row down by Delta = 0.25, which
+    puts it below its successor (the cascading effect, Sec. 4.4): about nx
+    iterations while the rest of the field stays settled."""
+    nx = shape[0]
+    ny = shape[1] if len(shape) > 1 else 1
+    nz = shape[2] if len(shape) > 2 else 1
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    f = (-0.2 * x - 0.01 * y - 0.001 * z).astype(np.float32)
+    g = f.copy()
+    for (yy, zz) in rows:
+        g[zz, yy, 1] = f[zz, yy, 2] - np.float32(0.05)
+    shp = tuple(reversed(shape))
+    return f.reshape(shp), g.reshape(shp)
+
+
+@pytest.mark.parametrize("shape,rows", [((300,), [(0, 0)]),
+                                        ((320, 40, 12), [(0, 0), (1, 0), (17, 5), (39, 11)])])
+def test_long_cascade_bit_exact(ctx, shape, rows):
+    """About 300 iterations, so the per-pass mark tags run through their
+    whole cycle (the pass that wipes the marks included), with most boxes
+    and chunks idle in every frontier pass."""
+    f, g = _ramp_cascade(shape, rows)
+    res, _ = _compare(ctx, f, g, 1.25, "ramp cascade", n_steps=5)
+    assert res["iterations"] > 254, res
+
+
 # ----------------------------------------------------------------------------
 # original event constraints (integral paths by pointer jumping) and the
 # extremum-graph certificate
