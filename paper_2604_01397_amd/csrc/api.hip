@@ -220,7 +220,7 @@ void layout_b(const FieldDev &fd, uint32_t K, Layout &L, size_t off[12]) {
   const size_t b = fd.dtype == 0 ? 4 : 8;
   const size_t kb = b;  // sort key bytes
   const uint32_t Kc = K ? K : 1;
-  off[0] = L.add(4 * (size_t)Kc + 4 * (((size_t)Kc + 31) / 32));  // cp_rank, cp_below
+  off[0] = L.add(4 * (size_t)Kc + 4 * (((size_t)Kc + 31) / 32) + ((size_t)Kc + 255) / 256);  // cp_rank, cp_below, oflag
   off[1] = L.add(4 * (size_t)Kc);  // cp_vtx
   off[2] = 0;
   off[3] = L.add(4 * (size_t)Kc);  // cp_idx
@@ -282,6 +282,7 @@ exz_status setup_phase_b(exz_ctx *ctx, FieldDev &fd, uint32_t K, Arena &B, hipSt
   char *bb = (char *)B.take(LB.total);
   fd.cp_rank = (uint32_t *)(bb + ob[0]);
   fd.cp_below = fd.cp_rank + (K ? K : 1);
+  fd.oflag = (uint8_t *)(fd.cp_below + ((K ? K : 1) + 31) / 32);
   fd.cp_vtx = (uint32_t *)(bb + ob[1]);
   fd.cp_idx = (uint32_t *)(bb + ob[3]);
   fd.cpr = bb + ob[4];

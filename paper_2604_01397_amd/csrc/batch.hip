@@ -619,6 +619,7 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       const uint32_t K = (uint32_t)fd.K;
       fd.cp_rank = (uint32_t *)(b + ob[k][0]);
       fd.cp_below = fd.cp_rank + (K ? K : 1);
+      fd.oflag = (uint8_t *)(fd.cp_below + ((K ? K : 1) + 31) / 32);
       fd.cp_vtx = (uint32_t *)(b + ob[k][1]);
       fd.cp_idx = (uint32_t *)(b + ob[k][3]);
       fd.cpr = b + ob[k][4];

@@ -101,6 +101,8 @@ struct FieldDev {
   uint32_t *cp_rank;    // K, vertex order: rank in f's order
   uint32_t *cp_below;   // (K + 31) / 32 words, bit r: the critical point of rank r + 1 has the
                         // lower vertex index of the pair (r, r + 1)
+  uint8_t *oflag;       // (K + 255) / 256: the tag of the last single-field apply that moved
+                        // a critical point of these 256 ranks (or the first of the next)
   void *cpr;            // K: current value of every critical point of f, in f's order
   uint32_t *cp_idx;     // K, rank -> vertex
   uint32_t *sad_rank;   // saddle order -> rank in the CP order (K capacity)

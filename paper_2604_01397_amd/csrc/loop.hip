@@ -108,12 +108,28 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
     }
   }
   if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
-  // (a frontier pass tags the chunks of its marks, for the apply after it)
-  if (order && dense)
+  if (order && dense) {
     for (; ob + 1 < K; ob += gridDim.x * per) order_quad<T>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
-  else if (order)
-    for (; ob + 1 < K; ob += gridDim.x * per)
-      order_quad<T, true>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
+  } else if (order) {
+    // A frontier pass tests only the pairs a value of which the last apply
+    // changed (the others are as at their last test, and so are the targets
+    // they named): each wave's 256 ranks of an item carry the tag of the
+    // last apply that moved one of them or the first rank after them.  Each
+    // lane reads the tag of one of its wave's items; the wave tests the
+    // items whose tag is the last pass's (and tags the chunks of its marks,
+    // for the apply after it).
+    const uint32_t prev = tag == 1 ? MARK_TAGS : tag - 1;
+    const uint32_t lane = threadIdx.x, wb = 256u * threadIdx.y, step = gridDim.x * per;
+    for (uint32_t k0 = 0; ob + k0 * step + 1 < K; k0 += 64) {
+      const uint32_t rb = ob + (k0 + lane) * step + wb;
+      unsigned long long live = __ballot(rb + 1 < K && glob(fd.oflag)[rb >> 8] == prev);
+      while (live) {
+        const uint32_t k = k0 + (uint32_t)(__ffsll(live) - 1);
+        live &= live - 1;
+        order_quad<T, true>(fd, ob + k * step + wb + 4u * lane, K, lane != 63, tag);
+      }
+    }
+  }
 }
 
 // Reference topology of f, box by box over the same persistent walk.

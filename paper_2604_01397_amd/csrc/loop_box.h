@@ -807,7 +807,7 @@ __device__ __forceinline__ void load_quad(const FieldDev &fd, uint32_t v, const 
 // Returns the vertices whose value or count moved, as bits 0..3.
 template <class T>
 __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, uint32_t m,
-                                              const QuadIn<T> &d, EditCount &ec) {
+                                              const QuadIn<T> &d, EditCount &ec, uint32_t otag) {
   T *G = (T *)fd.g;
   const T xiT = (T)fd.xiT, delta = (T)fd.delta;
   uint32_t moved = 0, cw = 0;
@@ -831,8 +831,16 @@ __device__ __forceinline__ uint32_t edit_quad(const FieldDev &fd, uint32_t v, ui
     }
     gn[c] = nv;
     // a critical point of f: the copy of its value, in f's order, that the
-    // order pass streams
-    if ((d.cpm >> c) & 1u) glob((T *)fd.cpr)[d.rank[c]] = nv;
+    // order pass streams, and (otag != 0) the tags of the rank groups whose
+    // pairs it belongs to, for the next frontier check
+    if ((d.cpm >> c) & 1u) {
+      const uint32_t r = d.rank[c];
+      glob((T *)fd.cpr)[r] = nv;
+      if (otag) {
+        glob(fd.oflag)[r >> 8] = (uint8_t)otag;
+        if ((r & 255u) == 0 && r) glob(fd.oflag)[(r - 1) >> 8] = (uint8_t)otag;
+      }
+    }
     moved |= 1u << c;
     ++ec.v[1];
     ec.v[4] += cn == 1;
@@ -899,7 +907,7 @@ __device__ __forceinline__ void apply_quad(const FieldDev &fd, uint32_t q, QuadH
   if (h.m) {
     QuadIn<T> d;
     load_quad<T>(fd, 4u * q, h, d);
-    moved = edit_quad<T>(fd, 4u * q, h.m, d, ec);
+    moved = edit_quad<T>(fd, 4u * q, h.m, d, ec, flag && fd.chunk_marks ? tag : 0u);
   }
   if (flag) mark_moved_boxes(fd, 4u * q, moved);
 }

@@ -284,6 +284,7 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint
     fd.cp_rank[vo] = r;
     ((T *)fd.cpr)[r] = ((const T *)fd.g)[v];
     below = r + 1 < K && sorted_vo[r + 1] < vo;
+    if ((r & 255u) == 0) fd.oflag[r >> 8] = 0;
   }
   const unsigned long long b = __ballot(below);
   const uint32_t lane = threadIdx.x & 63u;
