@@ -112,11 +112,126 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_setup(FieldDev fd) {
   }
 }
 
+// The same set-up four vertices per thread, for fields of 4k vertices whose
+// buffers allow vector accesses: values by 16-byte loads and stores, the
+// byte arrays a 32-bit word at a time.  Each bitmask word (64 vertices, 16
+// lanes of quads) is assembled from four ballots, one per position in the
+// quad.
+typedef float s_f32x4 __attribute__((ext_vector_type(4)));
+typedef double s_f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load4(const float *p, float *o) {
+  const s_f32x4 v = *glob(reinterpret_cast<const s_f32x4 *>(p));
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double *p, double *o) {
+  const s_f64x2 a = glob(reinterpret_cast<const s_f64x2 *>(p))[0];
+  const s_f64x2 b = glob(reinterpret_cast<const s_f64x2 *>(p))[1];
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+__device__ __forceinline__ void store4(float *p, const float *o) {
+  s_f32x4 v;
+  v.x = o[0]; v.y = o[1]; v.z = o[2]; v.w = o[3];
+  *glob(reinterpret_cast<s_f32x4 *>(p)) = v;
+}
+__device__ __forceinline__ void store4(double *p, const double *o) {
+  s_f64x2 a, b;
+  a.x = o[0]; a.y = o[1]; b.x = o[2]; b.y = o[3];
+  glob(reinterpret_cast<s_f64x2 *>(p))[0] = a;
+  glob(reinterpret_cast<s_f64x2 *>(p))[1] = b;
+}
+
+// Bit k of the low 16 bits of x moved to bit 4k.
+__device__ __forceinline__ unsigned long long spread4(unsigned long long x) {
+  x = (x | (x << 24)) & 0x000000FF000000FFull;
+  x = (x | (x << 12)) & 0x000F000F000F000Full;
+  x = (x | (x << 6)) & 0x0303030303030303ull;
+  x = (x | (x << 3)) & 0x1111111111111111ull;
+  return x;
+}
+
+template <class T>
+__global__ void __launch_bounds__(SETUP_BLOCK) k_setup_quad(FieldDev fd) {
+  const uint32_t q = blockIdx.x * SETUP_BLOCK + threadIdx.x;
+  const uint32_t n = (uint32_t)fd.n, nq = n / 4;
+  uint32_t cpn = 0;  // bit c: vertex 4q + c is a critical point of f
+  if (q < nq) {
+    const uint32_t v = 4u * q;
+    T f4[4], g4[4];
+    load4((const T *)fd.f + v, f4);
+    load4((const T *)fd.g_hat + v, g4);
+    const uint32_t code4 = *glob(reinterpret_cast<const uint32_t *>(fd.code + v));
+    const uint32_t low01 = *glob(reinterpret_cast<const uint32_t *>(fd.low + v));
+    const uint32_t low23 = *glob(reinterpret_cast<const uint32_t *>(fd.low + v + 2));
+    const uint32_t c04 = fd.resume ? *glob(reinterpret_cast<const uint32_t *>(fd.cnt + v)) : 0u;
+    const T xiT = (T)fd.xiT, delta = (T)fd.delta;
+    uint32_t err = 0, fe4 = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const T fi = f4[c], gi = g4[c];
+      const T L = lower_bound(fi, xiT);
+      if (!isfinite(fi) || !isfinite(gi))
+        err |= ERR_NONFINITE;
+      else if (gi < L || gi > upper_bound(fi, xiT))
+        err |= ERR_BOUND;
+      // the count of the edit that stores L (as in k_setup)
+      const uint32_t c0 = (c04 >> (8 * c)) & 255u;
+      uint32_t e = c0;
+      if (!(gi == L)) {
+        T g = gi;
+        for (e = c0 + 1; e <= (uint32_t)fd.N; ++e) {
+          const T cand = g - delta;
+          if (cand < L || cand == L) break;
+          g = cand;
+        }
+      }
+      fe4 |= min(e, 255u) << (8 * c);
+      const uint32_t code = (code4 >> (8 * c)) & 255u;
+      const uint32_t lw = ((c < 2 ? low01 : low23) >> (16 * (c & 1))) & 0xFFFFu;
+      const bool cp = (code & 15u) == SELF || (code >> 4) == SELF || (lw & LOW_SADDLE);
+      cpn |= (uint32_t)cp << c;
+    }
+    if (err) atomicOr(&fd.st->err, err);
+    *glob(reinterpret_cast<uint32_t *>(fd.fe + v)) = fe4;
+    if (fd.g != fd.g_hat) store4((T *)fd.g + v, g4);
+    if (!fd.resume) *glob(reinterpret_cast<uint32_t *>(fd.cnt + v)) = 0u;
+    *glob(reinterpret_cast<uint32_t *>(fd.tmark + v)) = 0u;
+    if ((v & 255u) == 0) fd.mchunk[v >> MARK_CHUNK_SHIFT] = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (v + c < (uint32_t)fd.ntiles) fd.bdirty[v + c] = 0;  // ntiles <= n
+  }
+  if (q < 16) *glob(reinterpret_cast<uint32_t *>(fd.tmark + n + 4u * q)) = 0u;  // padding
+  unsigned long long b[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) b[c] = __ballot((cpn >> c) & 1u);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t j = (q - lane) / 16u + lane;  // this lane's word (lanes 0..3)
+  if (lane < 4 && (unsigned long long)j * 64u < (unsigned long long)n) {
+    const uint32_t sh = 16u * lane;
+    unsigned long long word = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) word |= spread4((b[c] >> sh) & 0xFFFFull) << c;
+    fd.cpbits[j] = word;
+    fd.cpoff[j] = (uint32_t)__popcll(word);
+  }
+}
+
 // The reference topology box by box (staged through LDS), then validation,
-// copies and the critical-point bitmask from its codes.
+// copies and the critical-point bitmask from its codes (four vertices per
+// thread when the field allows it).
 hipError_t launch_setup(const FieldDev &fd, const uint32_t *conn, hipStream_t s) {
   const hipError_t e = launch_ref(fd, conn, s);
   if (e != hipSuccess) return e;
+  const bool quads = fd.vec && fd.n % 4 == 0 && (uintptr_t)fd.g_hat % 16 == 0;
+  if (quads) {
+    const int grid = (fd.n / 4 + SETUP_BLOCK - 1) / SETUP_BLOCK;
+    if (fd.dtype == 0)
+      hipLaunchKernelGGL(k_setup_quad<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd);
+    else
+      hipLaunchKernelGGL(k_setup_quad<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd);
+    return hipGetLastError();
+  }
   const int grid = (fd.n + SETUP_BLOCK - 1) / SETUP_BLOCK;
   if (fd.dtype == 0)
     hipLaunchKernelGGL(k_setup<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd);
@@ -256,8 +371,42 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_compact(FieldDev fd, void *k
   ((K *)keys_)[vo] = sort_key(F[i]);
 }
 
+// The same four vertices per thread (quads of a field of 4k vertices with
+// 16-byte aligned f): the quad's values in one load when it holds a
+// critical point.
+template <class T>
+__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_compact_quad(FieldDev fd, void *keys_,
+                                                                 uint32_t *vals) {
+  const uint32_t q = blockIdx.x * SETUP_BLOCK + threadIdx.x;
+  if (q >= (uint32_t)fd.n / 4) return;
+  const uint32_t v = 4u * q, sh = v & 63u;
+  const unsigned long long bits = fd.cpbits[v >> 6];
+  const uint32_t m = (uint32_t)(bits >> sh) & 15u;
+  if (!m) return;
+  uint32_t vo = fd.cpoff[v >> 6] + (uint32_t)__popcll(bits & ((1ull << sh) - 1ull));
+  T f4[4];
+  load4((const T *)fd.f + v, f4);
+  using K = decltype(sort_key(T(0)));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (!((m >> c) & 1u)) continue;
+    fd.cp_vtx[vo] = v + c;
+    vals[vo] = vo;
+    ((K *)keys_)[vo] = sort_key(f4[c]);
+    ++vo;
+  }
+}
+
 hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *, void *keys, uint32_t *vals,
                              hipStream_t s) {
+  if (fd.vec && fd.n % 4 == 0) {
+    const int grid = (fd.n / 4 + SETUP_BLOCK - 1) / SETUP_BLOCK;
+    if (fd.dtype == 0)
+      hipLaunchKernelGGL(k_cp_compact_quad<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, keys, vals);
+    else
+      hipLaunchKernelGGL(k_cp_compact_quad<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, keys, vals);
+    return hipGetLastError();
+  }
   const int grid = (fd.n + SETUP_BLOCK - 1) / SETUP_BLOCK;
   if (fd.dtype == 0)
     hipLaunchKernelGGL(k_cp_compact<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, keys, vals);
