@@ -415,23 +415,21 @@ hipError_t launch_cp_compact(const FieldDev &fd, const uint8_t *, void *keys, ui
   return hipGetLastError();
 }
 
-// After the stable sort of the keys (payload = vertex-order slot): per rank
-// in f's order the vertex and the current value (read in rank order, the
-// slot's vertex and value gathered), per slot its rank (a scattered store),
-// and per rank whether the next critical point has the lower vertex index
-// (slots follow vertex order, so the slots decide; one bit per rank, a word
-// per 32 ranks from a wave's ballot).
-template <class T>
-__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint32_t *sorted_vo) {
+// After the stable sort of the keys (payload = vertex-order slot), in two
+// passes that read nothing at random (scattered stores cost less here than
+// gathers).  In rank order: per slot its rank (a scattered store), and per
+// rank whether the next critical point has the lower vertex index (slots
+// follow vertex order, so the slots decide; one bit per rank, a word per 32
+// ranks from a wave's ballot).  Then in slot order: per rank in f's order
+// the vertex and its current value (scattered stores; g is read nearly in
+// order).
+__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_rank(FieldDev fd, const uint32_t *sorted_vo) {
   const uint32_t r = blockIdx.x * SETUP_BLOCK + threadIdx.x;
   const uint32_t K = (uint32_t)fd.K;
   bool below = false;
   if (r < K) {
     const uint32_t vo = sorted_vo[r];
-    const uint32_t v = fd.cp_vtx[vo];
-    fd.cp_idx[r] = v;
     fd.cp_rank[vo] = r;
-    ((T *)fd.cpr)[r] = ((const T *)fd.g)[v];
     below = r + 1 < K && sorted_vo[r + 1] < vo;
     if ((r & 255u) == 0) fd.oflag[r >> 8] = 0;
   }
@@ -441,13 +439,23 @@ __global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd, const uint
   if (lane == 32 && r < K) fd.cp_below[r >> 5] = (uint32_t)(b >> 32);
 }
 
+template <class T>
+__global__ void __launch_bounds__(SETUP_BLOCK) k_cp_init(FieldDev fd) {
+  const uint32_t vo = blockIdx.x * SETUP_BLOCK + threadIdx.x;
+  if (vo >= (uint32_t)fd.K) return;
+  const uint32_t v = fd.cp_vtx[vo], r = fd.cp_rank[vo];
+  fd.cp_idx[r] = v;
+  ((T *)fd.cpr)[r] = ((const T *)fd.g)[v];
+}
+
 hipError_t launch_cp_init(const FieldDev &fd, const uint32_t *sorted_vo, hipStream_t s) {
   if (fd.K == 0) return hipSuccess;
   const int grid = (fd.K + SETUP_BLOCK - 1) / SETUP_BLOCK;
+  hipLaunchKernelGGL(k_cp_rank, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
   if (fd.dtype == 0)
-    hipLaunchKernelGGL(k_cp_init<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
+    hipLaunchKernelGGL(k_cp_init<float>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd);
   else
-    hipLaunchKernelGGL(k_cp_init<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd, sorted_vo);
+    hipLaunchKernelGGL(k_cp_init<double>, dim3(grid), dim3(SETUP_BLOCK), 0, s, fd);
   return hipGetLastError();
 }
 

@@ -33,13 +33,19 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const K *keys, uint32_t co
   hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile of RS_TILE elements.  The tile is first
-// ordered by digit in LDS (stable: each wave ranks equal digits of its 64
-// elements with eight ballots, waves and rounds follow element order), then
-// written out run by run: consecutive threads write consecutive positions of
-// one digit's output range, so the stores coalesce.  offs is the scanned
-// digit-major histogram; the tile's own count of digit d is the difference
-// of two neighbouring entries.
+// Stable scatter of one tile of RS_TILE elements.  Wave w owns the tile's
+// elements w * 64 * RS_ITEMS .. (w + 1) * 64 * RS_ITEMS - 1 and ranks them in
+// order, round by round, against digit counters of its own in LDS (lanes
+// holding the same digit are found with eight ballots; the lowest of them
+// advances the counter after all have read it, so no barrier is needed
+// inside the wave's loop).  One barrier later the counters become each
+// wave's offset within each digit of the tile, the tile's digits are laid
+// out in LDS in digit order (an exclusive scan of the tile's counts), the
+// elements are placed there, and the tile is written out run by run:
+// consecutive threads write consecutive positions of one digit's output
+// range, so the stores coalesce.  offs is the scanned digit-major
+// histogram; the tile's own count of digit d is the difference of two
+// neighbouring entries.
 template <class K>
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uint32_t *vin, K *kout,
                                                          uint32_t *vout, uint32_t count, int shift,
@@ -48,40 +54,34 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uin
   __shared__ uint32_t sv[RS_TILE];
   __shared__ uint32_t gbase[256];   // output position of the tile's first element of digit d
   __shared__ uint32_t lstart[256];  // first LDS slot of digit d
-  __shared__ uint32_t lnext[256];   // next free LDS slot of digit d
   __shared__ uint32_t wcnt[RS_WAVES][256];
+  __shared__ uint32_t wtot[RS_WAVES];
   const int lane = __lane_id(), w = threadIdx.x >> 6, t = threadIdx.x;
   const uint32_t b = blockIdx.x;
   const uint32_t hidx = (uint32_t)t * nblocks + b;
   const uint32_t g0 = offs[hidx];
+  const uint32_t c = offs[hidx + 1] - g0;  // this tile's count of digit t
   gbase[t] = g0;
-  // exclusive scan of the tile's digit counts (256 threads, one per digit)
-  uint32_t c = offs[hidx + 1] - g0;
-  lstart[t] = c;
+#pragma unroll
+  for (int k = 0; k < RS_WAVES; ++k) wcnt[k][t] = 0;
   __syncthreads();
-  for (int d = 1; d < 256; d <<= 1) {
-    const uint32_t add = t >= d ? lstart[t - d] : 0u;
-    __syncthreads();
-    lstart[t] += add;
-    __syncthreads();
-  }
-  const uint32_t ls = lstart[t] - c;  // exclusive
-  __syncthreads();
-  lstart[t] = ls;
-  lnext[t] = ls;
   const unsigned long long below = (1ull << lane) - 1ull;
   const uint32_t tile = b * RS_TILE;
+  const uint32_t wbase = tile + (uint32_t)w * (64u * RS_ITEMS);
+  K key[RS_ITEMS];
+  uint32_t val[RS_ITEMS], rk[RS_ITEMS];  // rank within the wave's digit | digit << 16
+#pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
-    const uint32_t e = tile + r * RS_BLOCK + t;
+    const uint32_t e = wbase + (uint32_t)r * 64u + (uint32_t)lane;
     const bool valid = e < count;
-    K key = 0;
-    uint32_t val = 0, d = 0;
+    key[r] = 0;
+    val[r] = 0;
+    uint32_t d = 0;
     if (valid) {
-      key = kin[e];
-      val = vin[e];
-      d = (uint32_t)(key >> shift) & 255u;
+      key[r] = kin[e];
+      val[r] = vin[e];
+      d = (uint32_t)(key[r] >> shift) & 255u;
     }
-    // lanes of this wave holding the same digit
     unsigned long long m = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -89,30 +89,52 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uin
       const unsigned long long bb = __ballot(valid && on);
       m &= on ? bb : ~bb;
     }
-#pragma unroll
-    for (int k = 0; k < RS_WAVES; ++k) wcnt[k][t] = 0;
-    __syncthreads();
-    if (valid && lane == __ffsll((long long)m) - 1) wcnt[w][d] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = lnext[d] + (uint32_t)__popcll(m & below);
-      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-      sk[pos] = key;
-      sv[pos] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int k = 0; k < RS_WAVES; ++k) add += wcnt[k][t];
-    lnext[t] += add;
-    __syncthreads();
+    const uint32_t before = wcnt[w][d];
+    rk[r] = (before + (uint32_t)__popcll(m & below)) | (d << 16);
+    // the wave's LDS accesses complete in order: every lane has read the
+    // counter before its lowest lane advances it
+    if (valid && lane == __ffsll((long long)m) - 1) wcnt[w][d] = before + (uint32_t)__popcll(m);
   }
+  __syncthreads();
+  // per digit (thread t): each wave's offset within the tile's digit t
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < RS_WAVES; ++k) {
+    const uint32_t x = wcnt[k][t];
+    wcnt[k][t] = acc;
+    acc += x;
+  }
+  // exclusive scan of the tile's digit counts: waves, then across waves
+  uint32_t inc = c;
+#pragma unroll
+  for (int dd = 1; dd < 64; dd <<= 1) {
+    const uint32_t o = __shfl_up(inc, dd);
+    if (lane >= dd) inc += o;
+  }
+  if (lane == 63) wtot[w] = inc;
+  __syncthreads();
+  uint32_t woff = 0;
+#pragma unroll
+  for (int k = 0; k < RS_WAVES; ++k) woff += k < w ? wtot[k] : 0u;
+  lstart[t] = woff + inc - c;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const uint32_t e = wbase + (uint32_t)r * 64u + (uint32_t)lane;
+    if (e < count) {
+      const uint32_t d = rk[r] >> 16;
+      const uint32_t pos = lstart[d] + wcnt[w][d] + (rk[r] & 0xFFFFu);
+      sk[pos] = key[r];
+      sv[pos] = val[r];
+    }
+  }
+  __syncthreads();
   const uint32_t n_tile = min((uint32_t)RS_TILE, count - tile);
   for (uint32_t j = t; j < n_tile; j += RS_BLOCK) {
-    const K key = sk[j];
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const K k = sk[j];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
     const uint32_t pos = gbase[d] + (j - lstart[d]);
-    kout[pos] = key;
+    kout[pos] = k;
     vout[pos] = sv[j];
   }
 }
