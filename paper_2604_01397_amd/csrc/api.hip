@@ -698,15 +698,27 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
     HIP_OR_FAIL(hipEventRecord(ctx->poll_ev[slot], s));
     return EXZ_OK;
   };
-  // Adaptive chunks: 8 passes at first, then 16 while the latest known pass
-  // changed many values (the field cannot be near its fixpoint) and 4 once
-  // it did not, so that few launches run past the end.
+  // Adaptive chunks.  The host learns a pass's state a chunk late, so each
+  // chunk should end where the field can end at the earliest.  Once most
+  // values have settled, the number a pass changes falls by a factor of
+  // about 2.5 or more per pass, so a field whose last known pass changed c
+  // values needs at least log_2.5(c) more passes, then the frontier pass
+  // that finds the fixpoint and the dense one that confirms it: chunks reach
+  // that far (4 to 16 passes; 8 before any state is known).
   int slot = 0;
   const State *known = nullptr;
   st = issue_chunk(slot);
   if (st != EXZ_OK) return st;
   for (;;) {
-    if (ctx->poll == 0) chunk = !known ? 8 : known->busy ? 16 : 4;
+    if (ctx->poll == 0) {
+      if (!known) {
+        chunk = 8;
+      } else {
+        const double c = known->changed > 1 ? (double)known->changed : 1.0;
+        const int64_t end = known->passes + (int64_t)std::ceil(std::log(c) / std::log(2.5)) + 2;
+        chunk = (int)std::min<int64_t>(16, std::max<int64_t>(4, end - issued));
+      }
+    }
     st = issue_chunk(1 - slot);
     if (st != EXZ_OK) return st;
     HIP_OR_FAIL(hipEventSynchronize(ctx->poll_ev[slot]));

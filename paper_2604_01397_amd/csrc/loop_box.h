@@ -989,6 +989,8 @@ __device__ __forceinline__ void finalize_field(const FieldDev &fd) {
   }
   if (lane != 0) return;
   const uint32_t nt = v[0], ch = v[1];
+  st->ntargets = nt;
+  st->changed = ch;
   if (fd.trace && st->iterations < fd.trace_cap) {
     fd.trace[2 * st->iterations] = nt;
     fd.trace[2 * st->iterations + 1] = ch;
