@@ -235,9 +235,21 @@ def run_serving(torch, exactz, synth, serve, jobs, rate, plain=True):
     trace = synth.config4_specs(jobs, rate)
 
     def crop(e, off):
-        idx = [(torch.arange(e, device=src.device) + int(o)) % src_edge for o in off]
-        f = src.index_select(0, idx[0]).index_select(1, idx[1]).index_select(2, idx[2])
-        return f.contiguous()
+        # the periodic crop as at most 8 block copies into one new tensor (no
+        # temporaries of other sizes to fill the caching allocator)
+        f = torch.empty((e, e, e), dtype=src.dtype, device=src.device)
+
+        def runs(o):  # (source start, length, target start) of each piece
+            o = int(o) % src_edge
+            a = min(e, src_edge - o)
+            return [(o, a, 0)] + ([(0, e - a, a)] if e > a else [])
+
+        for (s0, l0, t0) in runs(off[0]):
+            for (s1, l1, t1) in runs(off[1]):
+                for (s2, l2, t2) in runs(off[2]):
+                    f[t0:t0 + l0, t1:t1 + l1, t2:t2 + l2].copy_(
+                        src[s0:s0 + l0, s1:s1 + l1, s2:s2 + l2])
+        return f
 
     # each block's eps (1e-3 of its range) before the served window: inside
     # it, a job's input is cut and quantised on the GPU with no host wait

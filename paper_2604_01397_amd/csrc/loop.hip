@@ -74,7 +74,10 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   const bool order = fd.mode != 1 && fd.K > 1;
   const uint32_t K = (uint32_t)fd.K, tag = st->tag;
   const uint32_t tid = threadIdx.y * 64 + threadIdx.x, per = 4u * 64u * TY;
-  uint32_t ob = blockIdx.x * per;  // this work-group's next item
+  // this work-group's next item (64-bit: a grid of one work-group per box
+  // can step past 2^32 ranks)
+  unsigned long long ob = (unsigned long long)blockIdx.x * per;
+  const unsigned long long ostep = (unsigned long long)gridDim.x * per;
   const bool dense = !fd.frontier || st->dense;
   if (dense) {
     for (uint32_t tile = w.first; tile < w.end; tile += w.stride) {
@@ -83,8 +86,8 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
       if (lead) done_v += box_vertices(fd, o, TY, TZ);
       __syncthreads();
       if (order && ob + 1 < K) {
-        order_quad<T>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
-        ob += gridDim.x * per;
+        order_quad<T>(fd, (uint32_t)ob + 4u * tid, K, threadIdx.x != 63, tag);
+        ob += ostep;
       }
     }
   } else {
@@ -109,7 +112,7 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
   }
   if (lead && done_v) atomicAdd(&st->checked, (unsigned long long)done_v);
   if (order && dense) {
-    for (; ob + 1 < K; ob += gridDim.x * per) order_quad<T>(fd, ob + 4u * tid, K, threadIdx.x != 63, tag);
+    for (; ob + 1 < K; ob += ostep) order_quad<T>(fd, (uint32_t)ob + 4u * tid, K, threadIdx.x != 63, tag);
   } else if (order) {
     // A frontier pass tests only the pairs a value of which the last apply
     // changed (the others are as at their last test, and so are the targets
@@ -118,15 +121,18 @@ __global__ void __launch_bounds__(64 * TY) k_check(FieldDev fd, const uint32_t *
     // lane reads the tag of one of its wave's items; the wave tests the
     // items whose tag is the last pass's (and tags the chunks of its marks,
     // for the apply after it).
+    // (rank positions in 64 bits: with one work-group per box, 64 steps of
+    // the grid exceed 2^32 ranks)
     const uint32_t prev = tag == 1 ? MARK_TAGS : tag - 1;
-    const uint32_t lane = threadIdx.x, wb = 256u * threadIdx.y, step = gridDim.x * per;
-    for (uint32_t k0 = 0; ob + k0 * step + 1 < K; k0 += 64) {
-      const uint32_t rb = ob + (k0 + lane) * step + wb;
+    const uint32_t lane = threadIdx.x, wb = 256u * threadIdx.y;
+    const unsigned long long step = ostep;
+    for (unsigned long long k0 = 0; ob + k0 * step + 1 < K; k0 += 64) {
+      const unsigned long long rb = ob + (k0 + lane) * step + wb;
       unsigned long long live = __ballot(rb + 1 < K && glob(fd.oflag)[rb >> 8] == prev);
       while (live) {
-        const uint32_t k = k0 + (uint32_t)(__ffsll(live) - 1);
+        const unsigned long long k = k0 + (unsigned long long)(__ffsll(live) - 1);
         live &= live - 1;
-        order_quad<T, true>(fd, ob + k * step + wb + 4u * lane, K, lane != 63, tag);
+        order_quad<T, true>(fd, (uint32_t)(ob + k * step + wb) + 4u * lane, K, lane != 63, tag);
       }
     }
   }

@@ -920,17 +920,20 @@ __device__ __forceinline__ void apply_quads(const FieldDev &fd, uint32_t q0, uin
   const uint32_t tag = fd.st->tag;
   const bool wipe = tag == MARK_TAGS;  // the last tag of the cycle: zero every mark
   if (SKIP && !busy && !wipe && chunk_pass(fd)) {
-    const uint32_t c0 = __builtin_amdgcn_readfirstlane(q0 >> 6), cs = stride >> 6;
-    const uint32_t nc = (nq + 63) >> 6, lane = __lane_id();
-    for (uint32_t s0 = 0; c0 + s0 * cs < nc; s0 += 64) {
-      const uint32_t c = c0 + (s0 + lane) * cs;
+    // (chunk and quad positions in 64 bits, whatever the grid)
+    const unsigned long long c0 = __builtin_amdgcn_readfirstlane(q0 >> 6), cs = stride >> 6;
+    const unsigned long long nc = (nq + 63) >> 6;
+    const uint32_t lane = __lane_id();
+    for (unsigned long long s0 = 0; c0 + s0 * cs < nc; s0 += 64) {
+      const unsigned long long c = c0 + (s0 + lane) * cs;
       unsigned long long live = __ballot(c < nc && glob(fd.mchunk)[c] == tag);
       if (!live) continue;
-      uint32_t q = q0 + (s0 + (uint32_t)(__ffsll(live) - 1)) * stride;
+      uint32_t q = (uint32_t)(q0 + (s0 + (unsigned long long)(__ffsll(live) - 1)) * stride);
       live &= live - 1;
       QuadHead h = quad_head(fd, q, nq, busy);
       for (;;) {
-        const uint32_t qn = live ? q0 + (s0 + (uint32_t)(__ffsll(live) - 1)) * stride : nq;
+        const uint32_t qn =
+            live ? (uint32_t)(q0 + (s0 + (unsigned long long)(__ffsll(live) - 1)) * stride) : nq;
         live &= live - 1;
         const QuadHead hn = quad_head(fd, qn, nq, busy);
         apply_quad<T>(fd, q, h, tag, false, flag, ec);

@@ -7,7 +7,13 @@ side stream while the admitted jobs keep iterating, advances every active
 job together with one batched step per tick (``exz_step``: shared launches,
 per-job state, per-job convergence), retires finished jobs, frees their
 memory and admits the next ones.  Admission is first come, first served;
-a job larger than the whole budget is rejected.
+a job larger than the whole budget is rejected.  Memory the budget does not
+see (a caching allocator's free blocks, say) can still make a job's
+allocation fail: the executor calls such an error transient, and the job
+goes back to the head of the queue, the executor gives back what it can
+(``reclaim``), and nothing is admitted until a running job has finished; a
+job is rejected for it only when nothing else runs and a retry after
+reclaiming fails too.
 
 Latency of a job = its completion (result polled, corrected field on the
 device) minus its arrival; aggregate throughput = field bytes of all
@@ -60,6 +66,7 @@ class Report:
     max_active: int
     max_bytes: int
     steps: int
+    requeued: int = 0   # admissions retried after a transient failure
 
     def completed(self):
         return [r for r in self.records if r.error is None and not np.isnan(r.completed)]
@@ -84,6 +91,7 @@ class Report:
             "max_active": self.max_active,
             "max_resident_GB": self.max_bytes / 1e9,
             "steps": self.steps,
+            "requeued": self.requeued,
         }
 
 
@@ -111,6 +119,12 @@ class Server:
         self.progress = progress
         self.progress_every = progress_every
 
+    def _transient(self, e) -> bool:
+        return bool(getattr(self.ex, "transient", lambda _e: False)(e))
+
+    def _reclaim(self):
+        getattr(self.ex, "reclaim", lambda: None)()
+
     def run(self, specs) -> Report:
         pending = collections.deque(sorted(specs, key=lambda s: (s.arrival, s.job_id)))
         queue = collections.deque()
@@ -119,6 +133,9 @@ class Server:
         used = 0
         max_active = max_bytes = steps = 0
         finished = 0
+        hold = False         # a transient failure: admit nothing until a job finishes
+        retried = set()      # jobs already retried with nothing else running
+        self.requeued = 0
         t0 = self.clock()
         last_report = 0.0
         while pending or queue or active:
@@ -134,7 +151,7 @@ class Server:
             if active:
                 self.ex.step([h for _, h, _ in active], self.iters)
                 steps += 1
-            while queue and len(active) < self.max_active:
+            while queue and len(active) < self.max_active and not hold:
                 spec = queue[0]
                 need = int(self.ex.footprint(spec))
                 if need > self.budget:
@@ -149,6 +166,16 @@ class Server:
                 try:
                     h = self.ex.start(spec)
                 except Exception as e:  # a bad request must not stop the server
+                    if self._transient(e) and (active or spec.job_id not in retried):
+                        # memory the budget does not see: retry this job later
+                        if not active:
+                            retried.add(spec.job_id)
+                        queue.appendleft(spec)
+                        rec.admitted = float("nan")
+                        self.requeued += 1
+                        self._reclaim()
+                        hold = bool(active)
+                        break
                     rec.error = "%s: %s" % (type(e).__name__, e)
                     continue
                 used += need
@@ -160,14 +187,23 @@ class Server:
                     self.sleep(max(0.0, min(pending[0].arrival - (self.clock() - t0), 0.05)))
                 continue
             still = []
+            back = []
             for rec, h, need in active:
                 try:
                     done, res = self.ex.poll(h)
                 except Exception as e:  # a job whose set-up failed (bad input)
-                    rec.error = "%s: %s" % (type(e).__name__, e)
                     self.ex.finish(h)
                     used -= need
+                    if self._transient(e) and (len(active) > 1 or rec.spec.job_id not in retried):
+                        if len(active) == 1:
+                            retried.add(rec.spec.job_id)
+                        back.append(rec.spec)
+                        rec.admitted = float("nan")
+                        self.requeued += 1
+                        continue
+                    rec.error = "%s: %s" % (type(e).__name__, e)
                     finished += 1
+                    hold = False
                     continue
                 if done:
                     rec.completed = self.clock() - t0
@@ -177,6 +213,7 @@ class Server:
                         rec.outputs = out
                     used -= need
                     finished += 1
+                    hold = False
                 else:
                     # the admission estimate gives way to the real footprint
                     # once the job's set-up has counted its critical points
@@ -186,8 +223,13 @@ class Server:
                         need = real
                     still.append((rec, h, need))
             active = still
+            if back:  # requeued in arrival order, ahead of the waiting jobs
+                queue.extendleft(reversed(back))
+                self._reclaim()
+                hold = bool(active)
         wall = self.clock() - t0
-        return Report([records[k] for k in sorted(records)], wall, max_active, max_bytes, steps)
+        return Report([records[k] for k in sorted(records)], wall, max_active, max_bytes, steps,
+                      self.requeued)
 
 
 class DeviceExecutor:
@@ -237,6 +279,18 @@ class DeviceExecutor:
         work = self.exactz.workspace_bytes(shape_xyz, self.exactz.F32 if b == 4 else self.exactz.F64,
                                            n_steps=self.n_steps, num_critical=min(k, n))
         return work + 2 * spec.field_bytes + n  # f, g (in place), counts
+
+    def transient(self, e) -> bool:
+        """An allocation failure: the library's out-of-memory status, or the
+        caching allocator's while the job's inputs are made."""
+        if isinstance(e, self.exactz.ExactzError):
+            return e.status == self.exactz.E_NOMEM
+        return isinstance(e, self.torch.cuda.OutOfMemoryError)
+
+    def reclaim(self):
+        """Returns the caching allocator's free blocks to the device, where
+        the library's allocations can use them."""
+        self.torch.cuda.empty_cache()
 
     def footprint_of(self, spec, result) -> Optional[int]:
         """The job's real footprint once its set-up has run, else None."""

@@ -188,6 +188,29 @@ def test_tile_shape_invariance(ctx, tile_y, tile_z):
     assert r["iterations"] == rref["iterations"]
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_one_group_per_box_large_grid(ctx, dtype):
+    """One work-group per box on a field of 2^26 vertices (box 64 x 8 x 4:
+    32768 work-groups, whose grid strides over the critical-point ranks
+    pass 2^32 within 64 steps) gives the persistent grid's result, through
+    the dense and the frontier passes."""
+    c = synth.case_grf3d((512, 512, 256), seed=41, slope=-11.0 / 3.0, rel=1e-4, dtype=dtype,
+                         quantizer="lorenzo")
+    print("case: 512x512x256", np.dtype(dtype).name, "box 8x4, grid 0 vs persistent", flush=True)
+    f, g = _dev(c.f), _dev(c.g_hat)
+    ref, cref, rref = ctx.correct(f, g, c.xi)
+    ctx.set_option("tile", 804)
+    ctx.set_option("grid", 0)
+    try:
+        out, cout, r = ctx.correct(f, g, c.xi)
+    finally:
+        ctx.set_option("tile", 0)
+        ctx.set_option("grid", -1)
+    torch.cuda.synchronize()
+    assert r["iterations"] == rref["iterations"] and r["iterations"] > 5, (r, rref)
+    assert torch.equal(out, ref) and torch.equal(cout, cref)
+
+
 @pytest.mark.parametrize("poll", [1, 3, 64])
 def test_poll_interval_invariance(ctx, poll):
     c = synth.case_gauss2d(100, seed=7, rel=1e-3)

@@ -200,3 +200,85 @@ def test_admission_estimate_gives_way_to_the_real_footprint():
     # two admitted at 100 each; after their first poll they count 50 each,
     # so the third is admitted before either finishes
     assert rep.max_active == 3
+
+
+class TightExecutor(SimExecutor):
+    """Memory the budget does not see: allocations fail (transiently) while
+    more than `room` bytes are live, until `reclaim` is called once."""
+
+    def __init__(self, clock, room, **kw):
+        super().__init__(clock, **kw)
+        self.room = room
+        self.reclaims = 0
+
+    def transient(self, e):
+        return isinstance(e, MemoryError)
+
+    def reclaim(self):
+        self.reclaims += 1
+
+    def start(self, spec):
+        if self.used + spec.meta["bytes"] > self.room:
+            raise MemoryError("device allocation failed")
+        return super().start(spec)
+
+
+def test_transient_allocation_failures_requeue_jobs():
+    """Jobs whose allocation fails while others run go back to the head of
+    the queue and finish later, in arrival order; none is rejected."""
+    clk = VirtualClock()
+    ex = TightExecutor(clk, room=1200)
+    specs = _trace(60, rate=2000.0, seed=5)
+    rep = Server(ex, budget_bytes=5000, max_active=16, clock=clk, sleep=clk.sleep).run(specs)
+    s = rep.summary()
+    assert s["completed"] == 60 and s["rejected"] == 0, s
+    assert s["requeued"] > 0 and ex.reclaims > 0
+    starts = [j for ev, j, _ in ex.log if ev == "start"]
+    assert starts == sorted(starts)  # first come, first served despite the retries
+    assert ex.peak <= 1200
+
+
+def test_transient_failure_with_nothing_running_is_rejected():
+    """A job that cannot be allocated even alone, after a reclaim, is
+    rejected instead of being retried for ever."""
+    clk = VirtualClock()
+    ex = TightExecutor(clk, room=250)
+    specs = [JobSpec(0, 0.0, (4, 4, 4), 256, meta={"bytes": 400, "need": 3}),
+             JobSpec(1, 0.01, (4, 4, 4), 256, meta={"bytes": 200, "need": 3})]
+    rep = Server(ex, budget_bytes=5000, max_active=4, clock=clk, sleep=clk.sleep).run(specs)
+    s = rep.summary()
+    assert s["completed"] == 1 and s["rejected"] == 1, s
+    assert rep.records[0].error is not None and "MemoryError" in rep.records[0].error
+
+
+class LateFailExecutor(SimExecutor):
+    """The set-up of some jobs fails on the device (transiently) the first
+    time; the failure shows at the job's first poll."""
+
+    def __init__(self, clock, late_ids, **kw):
+        super().__init__(clock, **kw)
+        self.late = set(late_ids)
+        self.reclaims = 0
+
+    def transient(self, e):
+        return isinstance(e, MemoryError)
+
+    def reclaim(self):
+        self.reclaims += 1
+
+    def poll(self, h):
+        if h["id"] in self.late:
+            self.late.discard(h["id"])
+            raise MemoryError("critical-point workspace did not fit")
+        return super().poll(h)
+
+
+def test_transient_setup_failure_at_poll_restarts_the_job():
+    clk = VirtualClock()
+    ex = LateFailExecutor(clk, late_ids=(3, 4, 9))
+    specs = _trace(20, rate=500.0, seed=8)
+    rep = Server(ex, budget_bytes=4000, max_active=8, clock=clk, sleep=clk.sleep).run(specs)
+    s = rep.summary()
+    assert s["completed"] == 20 and s["rejected"] == 0 and s["requeued"] == 3, s
+    assert [j for ev, j, _ in ex.log if ev == "start"].count(3) == 2
+    assert not ex.live  # every started job was finished (released)
