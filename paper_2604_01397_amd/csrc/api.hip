@@ -45,7 +45,7 @@ hipError_t Arena::reserve(size_t bytes) {
   }
   if (bytes <= cap) return hipSuccess;
   release();
-  const size_t want = bytes + bytes / 8 + 4096;
+  const size_t want = exact ? bytes : bytes + bytes / 8 + 4096;
   if (budget && budget->limit && budget->used + want > budget->limit) {
     // the slack is a convenience: fall back to the exact size before failing
     if (budget->used + bytes > budget->limit) return hipErrorOutOfMemory;

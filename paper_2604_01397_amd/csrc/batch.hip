@@ -827,6 +827,7 @@ exz_status job_begin(exz_ctx *ctx, const exz_field *field, void *stream, exz_job
   exz_job *job = new exz_job();
   job->ctx = ctx;
   job->A.budget = job->B.budget = &ctx->budget;  // the job's workspace counts against the budget
+  job->A.exact = job->B.exact = true;             // a job's arenas are never reused
   job->params = field->params;
   std::memset(&job->result, 0, sizeof job->result);
   job->result.certified = -1;

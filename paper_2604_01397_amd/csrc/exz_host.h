@@ -30,6 +30,7 @@ struct Arena {
   char *end = nullptr;          // fixed: end of the usable memory
   const Arena *after = nullptr; // fixed: start after this arena's carving
   Budget *budget = nullptr;     // charged for what this arena allocates
+  bool exact = false;           // allocate exactly what is asked (no growth slack)
   hipError_t reserve(size_t bytes);  // resets the carve offset
   void *take(size_t bytes);
   void release();

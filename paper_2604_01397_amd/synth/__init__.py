@@ -380,7 +380,10 @@ def quantize_uniform_device(f, eps: float, checked: bool = True):
     enforcement run unconditionally (a round that finds nothing outside the
     band changes nothing, so the result equals the checked one whenever two
     rounds suffice, which one ulp of float32 rounding always does; a value
-    still outside the band would be rejected by the library's validation)."""
+    still outside the band would be rejected by the library's validation).
+
+    The arithmetic is elementwise; it runs over chunks of 2^25 values, so
+    its float64 temporaries stay small whatever the block size."""
     import torch
 
     if f.dtype != torch.float32:
@@ -388,13 +391,20 @@ def quantize_uniform_device(f, eps: float, checked: bool = True):
     # the bin as a device tensor: torch divides by a Python scalar through its
     # reciprocal, which can round differently from numpy's true division
     b = torch.full((), 2.0 * eps, dtype=torch.float64, device=f.device)
-    q = torch.round(f.double() / b) * b  # round half to even, as np.rint
-    g = q.to(torch.float32)
-    for _ in range(8 if checked else 2):
-        bad = (g.double() - f.double()).abs() > eps
-        if checked and not bool(bad.any()):
-            return g
-        g = torch.where(bad, torch.nextafter(g, f), g)
-    if not checked:
-        return g
-    raise RuntimeError("band enforcement did not converge")
+    flat = f.reshape(-1)
+    out = torch.empty_like(flat)
+    chunk = 1 << 25
+    for k0 in range(0, flat.numel(), chunk):
+        fc = flat[k0:k0 + chunk]
+        fd = fc.double()
+        g = (torch.round(fd / b) * b).to(torch.float32)  # round half to even, as np.rint
+        for _ in range(8 if checked else 2):
+            bad = (g.double() - fd).abs() > eps
+            if checked and not bool(bad.any()):
+                break
+            g = torch.where(bad, torch.nextafter(g, fc), g)
+        else:
+            if checked:
+                raise RuntimeError("band enforcement did not converge")
+        out[k0:k0 + chunk] = g
+    return out.reshape(f.shape)
