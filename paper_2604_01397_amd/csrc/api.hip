@@ -664,7 +664,6 @@ exz_status exz_correct_impl(exz_ctx *ctx, const void *f, const void *g_hat, void
                    C, &lab_g, s);
   if (st != EXZ_OK) return st;
   HIP_OR_FAIL(hipEventRecord(ctx->ev_setup, s));
-  fd.chunk_marks = 1;  // the iterations below run the single-field kernels
 
   // Iterations are issued in chunks; each chunk ends with an asynchronous
   // copy of the device state into one of two pinned slots.  The host keeps

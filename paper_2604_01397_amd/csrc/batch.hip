@@ -55,7 +55,11 @@ __global__ void __launch_bounds__(64 * TY)
         __syncthreads();  // every thread has read the flag (frontier pass)
         if (threadIdx.x == 0 && threadIdx.y == 0) fd.bdirty[tile] = 0;
       }
-      check_box<T, TY, TZ>(fd, box_of(fd, tile, TY, TZ), L);
+      // (a frontier pass tags the chunks of its marks, for the apply after it)
+      if (chunk_pass(fd))
+        check_box<T, TY, TZ, true>(fd, box_of(fd, tile, TY, TZ), L);
+      else
+        check_box<T, TY, TZ>(fd, box_of(fd, tile, TY, TZ), L);
     }
     __syncthreads();
   }
@@ -89,9 +93,9 @@ __global__ void __launch_bounds__(APPLY_BLOCK) k_apply_batch(const FieldDev *__r
       const uint32_t q0 = (it - base[k]) * item_quads;
       const uint32_t nq = min(((uint32_t)fd.n + 3) / 4, q0 + item_quads);
       if (fd.dtype == 0)
-        apply_quads<float>(fd, q0 + threadIdx.x, APPLY_BLOCK, nq, ec);
+        apply_quads<float, true>(fd, q0 + threadIdx.x, APPLY_BLOCK, nq, ec);
       else
-        apply_quads<double>(fd, q0 + threadIdx.x, APPLY_BLOCK, nq, ec);
+        apply_quads<double, true>(fd, q0 + threadIdx.x, APPLY_BLOCK, nq, ec);
     }
   }
   if (nf) flush_counts<APPLY_BLOCK / 64>(fields[field[kc]].st, ec, blockIdx.x);
@@ -112,11 +116,21 @@ __global__ void __launch_bounds__(256) k_order_batch(const FieldDev *__restrict_
     const uint32_t r0 = (it - base[k]) * ORD_ITEM;
     const uint32_t lim = min((uint32_t)fd.K, r0 + ORD_ITEM + 1);  // the item's pairs only
     const uint32_t tag = fd.st->tag;
+    // a frontier pass tests only the wave's 256 ranks whose tag is the last
+    // pass's (as the single-field check does), and tags the chunks it marks
+    const bool front = chunk_pass(fd);
+    const uint32_t prev = tag == 1 ? MARK_TAGS : tag - 1;
     for (uint32_t j = 0; j < ORD_ITEM && r0 + j + 1 < lim; j += 1024) {
-      if (fd.dtype == 0)
-        order_quad<float>(fd, r0 + j + 4 * threadIdx.x, lim, __lane_id() != 63, tag);
-      else
-        order_quad<double>(fd, r0 + j + 4 * threadIdx.x, lim, __lane_id() != 63, tag);
+      const uint32_t rw = r0 + j + 256u * (threadIdx.x >> 6);  // this wave's first rank
+      if (front && !(rw + 1 < lim && glob(fd.oflag)[rw >> 8] == prev)) continue;
+      const uint32_t r = r0 + j + 4 * threadIdx.x;
+      if (fd.dtype == 0) {
+        if (front) order_quad<float, true>(fd, r, lim, __lane_id() != 63, tag);
+        else order_quad<float>(fd, r, lim, __lane_id() != 63, tag);
+      } else {
+        if (front) order_quad<double, true>(fd, r, lim, __lane_id() != 63, tag);
+        else order_quad<double>(fd, r, lim, __lane_id() != 63, tag);
+      }
     }
   }
 }

@@ -82,7 +82,6 @@ struct FieldDev {
   int32_t grid_blocks;       // stencil grid: 0 one block per box, < 0 persistent default, > 0 fixed
   int32_t trace_cap;
   int32_t frontier;     // 1: re-check only boxes whose closed neighbourhood changed
-  int32_t chunk_marks;  // 1 (single-field loop): frontier passes tag the chunks they mark
   int32_t ty_shift, tz_shift;  // log2 of tile_y / tile_z
   int32_t vec;          // f, g 16-byte and cnt 4-byte aligned: apply reads four vertices at once
   int32_t dlt[16];      // linear index offset of each slot (dlt[SELF] = 0)
@@ -159,13 +158,12 @@ __device__ __forceinline__ uint32_t next_field_uniform(const uint32_t *base, uin
 // tag zeroes the whole array, so no mark outlives the cycle of tags.  The
 // 256-vertex chunk of a mark gets the tag too; a chunk tag left over from an
 // earlier cycle only makes apply visit a chunk without marks.
-// Chunks are tagged (CH) only in the frontier passes of the single-field
-// loop, which mark few vertices; the apply after such a pass skips untagged
-// chunks.
+// Chunks are tagged (CH) only in frontier passes, which mark few vertices;
+// the apply after such a pass skips untagged chunks.
 constexpr uint32_t MARK_TAGS = 254;
 constexpr uint32_t MARK_CHUNK_SHIFT = 8;
 __device__ __forceinline__ bool chunk_pass(const FieldDev &fd) {
-  return fd.chunk_marks && fd.frontier && !fd.st->dense;
+  return fd.frontier && !fd.st->dense;
 }
 template <bool CH = false>
 __device__ __forceinline__ void mark_target(const FieldDev &fd, uint32_t t, uint32_t tag) {

@@ -907,7 +907,7 @@ __device__ __forceinline__ void apply_quad(const FieldDev &fd, uint32_t q, QuadH
   if (h.m) {
     QuadIn<T> d;
     load_quad<T>(fd, 4u * q, h, d);
-    moved = edit_quad<T>(fd, 4u * q, h.m, d, ec, flag && fd.chunk_marks ? tag : 0u);
+    moved = edit_quad<T>(fd, 4u * q, h.m, d, ec, flag ? tag : 0u);
   }
   if (flag) mark_moved_boxes(fd, 4u * q, moved);
 }

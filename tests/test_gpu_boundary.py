@@ -102,8 +102,9 @@ def test_context_budget():
 
 def test_workspace_bytes_k_prices_a_job():
     """exz_workspace_bytes_k with a job's real number of critical points is
-    what the job's set-up reserves (the context adds at most an eighth plus
-    4 KiB of slack to each of its two reservations)."""
+    what the job's set-up reserves: a job's two reservations are exact, and
+    the counts live in the caller's buffer here (the binding always passes
+    one), so the job holds the priced bytes less those n."""
     from paper_2604_01397_amd import exactz
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -120,7 +121,8 @@ def test_workspace_bytes_k_prices_a_job():
         print("job reserved", delta, "bytes, K =", k, flush=True)
         want = exactz.workspace_bytes((48, 48, 48), num_critical=k)
         assert 0 < k < 48 ** 3
-        assert want <= delta <= want + want // 8 + 2 * 4096 + 512
+        n = 48 ** 3
+        assert want - n - 2 * 256 <= delta <= want - n + 2 * 256, (want, delta)
         assert want < exactz.workspace_bytes((48, 48, 48))  # the worst case (K = n)
         job.release()
     finally:
