@@ -129,8 +129,9 @@ exz_status exz_ctx_destroy(exz_ctx *ctx);
  *   "profile"  0/1: record device events around every check pass and
  *              report check_launches / check_ms / check_vertices;
  *   "poll"     iterations issued between two host polls (1..256; default:
- *              adaptive: 4, then 8, then 16 while the last pass the host
- *              saw changed more than n/64 values and 4 once it did not);
+ *              adaptive: 4, then 8, then chunks of 4..16 that reach the
+ *              earliest pass the field can end at, from the last pass the
+ *              host saw and the values it changed);
  *   "graph"    0/1: replay the iterations between polls from a captured
  *              hipGraph (batched calls; default 1);
  *   "tile"     check box 64 x tile_y x tile_z given as tile_y * 100 + tile_z;
@@ -141,17 +142,24 @@ exz_status exz_ctx_destroy(exz_ctx *ctx);
  *   "grid"     check work-groups: -1 persistent (default), 0 one per box,
  *              > 0 that many (persistent);
  *   "frontier" 0/1: after the first pass, re-check only boxes whose check
- *              reads a value the last apply changed: a vertex of the box or
- *              its halo, or the successor in f's order of one of its
- *              critical points (reformulated mode; default 1).  A pass that
- *              changes nothing is followed by a check of every box;
+ *              reads a value the last apply changed (a vertex of the box or
+ *              its halo), and test the order of the critical points only
+ *              for the ranks next to a moved one (reformulated mode;
+ *              default 1).  A pass that changes nothing is followed by a
+ *              check of every box;
  *   "btile3" / "btile2"  boxes of the 3D / 1D-2D members of batched calls
  *              and of jobs created afterwards (tile_y * 100 + tile_z; 2D
  *              boxes need tile_z = 1; 0 = 4 x 8 and 16 x 1).  A plain
  *              "tile" also sets the 3D box of batches when "btile3" is 0;
  *   "bgrid_box" / "bgrid_apply"  work-group caps of the batched check and
  *              apply passes (0 = 8 resp. 16 per compute unit);
- *   "bitem"    batched apply item size in quads per thread (1..256; 0 = 16).
+ *   "bitem"    batched apply item size in quads per thread (1..256; 0 = 16);
+ *   "job_pool" bytes of released jobs' workspace the context keeps for
+ *              later jobs (default 32 GiB; 0 frees each at once).  Taking
+ *              pooled memory needs no allocation and freeing into the pool
+ *              no wait for the device; pooled bytes count as in use, and
+ *              an allocation that fails frees the pool and tries again;
+ *   "trim"     frees the pooled job workspace now (value ignored).
  * Returns EXZ_E_INVALID for an unknown key or value. */
 exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value);
 

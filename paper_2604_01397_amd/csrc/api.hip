@@ -27,10 +27,55 @@ void Arena::release() {
     fixed = false;
     return;
   }
-  if (base) (void)hipFree(base);
-  if (budget) budget->used -= cap;
+  if (base && pool) {
+    pool->give(base, cap);  // stays charged to the budget while pooled
+  } else {
+    if (base) (void)hipFree(base);
+    if (budget) budget->used -= cap;
+  }
   base = nullptr;
   cap = off = 0;
+}
+
+char *Pool::take(size_t need, size_t &got) {
+  size_t best = blocks.size();
+  for (size_t k = 0; k < blocks.size(); ++k) {
+    const size_t b = blocks[k].bytes;
+    if (b >= need && b <= need + need / 4 + ((size_t)1 << 20) &&
+        (best == blocks.size() || b < blocks[best].bytes))
+      best = k;
+  }
+  if (best == blocks.size()) return nullptr;
+  char *p = blocks[best].p;
+  got = blocks[best].bytes;
+  bytes -= got;
+  blocks[best] = blocks.back();
+  blocks.pop_back();
+  return p;
+}
+
+void Pool::give(char *p, size_t n) {
+  blocks.push_back(Block{p, n});
+  bytes += n;
+  while (bytes > cap && !blocks.empty()) {  // past the cap: free the largest
+    size_t big = 0;
+    for (size_t k = 1; k < blocks.size(); ++k)
+      if (blocks[k].bytes > blocks[big].bytes) big = k;
+    (void)hipFree(blocks[big].p);
+    bytes -= blocks[big].bytes;
+    if (budget) budget->used -= blocks[big].bytes;
+    blocks[big] = blocks.back();
+    blocks.pop_back();
+  }
+}
+
+void Pool::trim() {
+  for (const Block &b : blocks) {
+    (void)hipFree(b.p);
+    if (budget) budget->used -= b.bytes;
+  }
+  blocks.clear();
+  bytes = 0;
 }
 
 hipError_t Arena::reserve(size_t bytes) {
@@ -45,13 +90,28 @@ hipError_t Arena::reserve(size_t bytes) {
   }
   if (bytes <= cap) return hipSuccess;
   release();
+  if (pool) {  // a pooled block is already charged to the budget
+    size_t got = 0;
+    if (char *p = pool->take(bytes, got)) {
+      base = p;
+      cap = got;
+      return hipSuccess;
+    }
+  }
   const size_t want = exact ? bytes : bytes + bytes / 8 + 4096;
+  if (pool && pool->bytes && budget && budget->limit && budget->used + bytes > budget->limit)
+    pool->trim();  // pooled memory gives way to a job that needs it
   if (budget && budget->limit && budget->used + want > budget->limit) {
     // the slack is a convenience: fall back to the exact size before failing
     if (budget->used + bytes > budget->limit) return hipErrorOutOfMemory;
   }
   const size_t got = (budget && budget->limit && budget->used + want > budget->limit) ? bytes : want;
   hipError_t e = hipMalloc(&base, got);
+  if (e != hipSuccess && pool && pool->bytes) {  // the device is full: free the pool, try again
+    (void)hipGetLastError();
+    pool->trim();
+    e = hipMalloc(&base, got);
+  }
   if (e != hipSuccess) {
     base = nullptr;
     (void)hipGetLastError();
@@ -386,6 +446,7 @@ exz_status exz_ctx_create(int device, size_t hbm_budget_bytes, exz_ctx **out) {
   ctx->budget.limit = hbm_budget_bytes;
   for (Arena *a : {&ctx->A, &ctx->B, &ctx->C, &ctx->BA, &ctx->BB, &ctx->BC, &ctx->H})
     a->budget = &ctx->budget;
+  ctx->job_pool.budget = &ctx->budget;
   // events of the single-field driver, created here so that a correction
   // call creates nothing
   if (hipEventCreate(&ctx->ev_start) != hipSuccess || hipEventCreate(&ctx->ev_setup) != hipSuccess ||
@@ -417,7 +478,8 @@ exz_status exz_ctx_destroy(exz_ctx *ctx) {
   if (!ctx) return EXZ_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  free_graveyard(ctx);
+  free_graveyard(ctx);  // (their arenas go to the pool, freed next)
+  ctx->job_pool.trim();
   ctx->A.release();
   ctx->B.release();
   ctx->C.release();
@@ -474,6 +536,12 @@ exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value) {
     ctx->tile_z = tz;
   } else if (k == "frontier") {  // 1: re-check only changed boxes (reformulated mode)
     ctx->frontier = value != 0;
+  } else if (k == "job_pool") {  // bytes of freed job arenas kept for later jobs
+    if (value < 0) return fail(ctx, EXZ_E_INVALID, "job_pool must be >= 0");
+    ctx->job_pool.cap = (size_t)value;
+    if (ctx->job_pool.bytes > ctx->job_pool.cap) ctx->job_pool.trim();
+  } else if (k == "trim") {  // free the pooled job arenas now (waits for the device)
+    ctx->job_pool.trim();
   } else if (k == "grid") {  // stencil work-groups: -1 persistent (default), 0 one per box
     if (value < -1 || value > (1 << 24)) return fail(ctx, EXZ_E_INVALID, "grid must be -1..2^24");
     ctx->grid_blocks = (int)value;

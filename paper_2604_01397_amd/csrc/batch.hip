@@ -768,14 +768,27 @@ bool job_quiet(const exz_job *job) {
   return true;
 }
 
+// (the job's work has ended: its events and pinned block go to the
+// context's spares, its arenas to the pool)
 void free_job(exz_job *job) {
-  for (hipEvent_t e : {job->ready, job->a_done})
-    if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : job->polled)
-    if (e) (void)hipEventDestroy(e);
+  exz_ctx *ctx = job->ctx;
+  auto spare_event = [&](hipEvent_t e) {
+    if (!e) return;
+    if (ctx->spare_events.size() < exz_ctx::SPARE_JOBS * (2 + exz_job::NSTATE))
+      ctx->spare_events.push_back(e);
+    else
+      (void)hipEventDestroy(e);
+  };
+  for (hipEvent_t e : {job->ready, job->a_done}) spare_event(e);
+  for (hipEvent_t e : job->polled) spare_event(e);
   job->A.release();
   job->B.release();
-  if (job->pinned) (void)hipHostFree(job->pinned);
+  if (job->pinned) {
+    if (ctx->spare_pinned.size() < exz_ctx::SPARE_JOBS)
+      ctx->spare_pinned.push_back(job->pinned);
+    else
+      (void)hipHostFree(job->pinned);
+  }
   delete job;
 }
 
@@ -841,7 +854,8 @@ exz_status job_begin(exz_ctx *ctx, const exz_field *field, void *stream, exz_job
   exz_job *job = new exz_job();
   job->ctx = ctx;
   job->A.budget = job->B.budget = &ctx->budget;  // the job's workspace counts against the budget
-  job->A.exact = job->B.exact = true;             // a job's arenas are never reused
+  job->A.exact = job->B.exact = true;             // exact sizes, handed to the pool when freed
+  job->A.pool = job->B.pool = &ctx->job_pool;
   job->params = field->params;
   std::memset(&job->result, 0, sizeof job->result);
   job->result.certified = -1;
@@ -849,15 +863,22 @@ exz_status job_begin(exz_ctx *ctx, const exz_field *field, void *stream, exz_job
   job->last = (hipStream_t)stream;
   job->phase = 0;
   exz_status st = EXZ_OK;
-  if (hipHostMalloc((void **)&job->pinned, sizeof(exz_job::Pinned), hipHostMallocDefault) !=
-      hipSuccess) {
+  if (!ctx->spare_pinned.empty()) {  // a freed job's block (its work has ended)
+    job->pinned = (exz_job::Pinned *)ctx->spare_pinned.back();
+    ctx->spare_pinned.pop_back();
+  } else if (hipHostMalloc((void **)&job->pinned, sizeof(exz_job::Pinned), hipHostMallocDefault) !=
+             hipSuccess) {
     job->pinned = nullptr;
     st = fail_b(ctx, EXZ_E_NOMEM, "hipHostMalloc failed");
   }
   std::vector<hipEvent_t *> evs = {&job->a_done, &job->ready};
   for (hipEvent_t &e : job->polled) evs.push_back(&e);
   for (hipEvent_t *e : evs) {
-    if (st == EXZ_OK && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+    if (st != EXZ_OK) break;
+    if (!ctx->spare_events.empty()) {  // completed events of freed jobs
+      *e = ctx->spare_events.back();
+      ctx->spare_events.pop_back();
+    } else if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
       *e = nullptr;
       st = fail_b(ctx, EXZ_E_HIP, "hipEventCreateWithFlags failed");
     }
@@ -886,6 +907,10 @@ exz_status job_begin(exz_ctx *ctx, const exz_field *field, void *stream, exz_job
 void free_graveyard(exz_ctx *ctx) {
   for (exz_job *j : ctx->graveyard) free_job(j);
   ctx->graveyard.clear();
+  for (void *p : ctx->spare_pinned) (void)hipHostFree(p);
+  ctx->spare_pinned.clear();
+  for (hipEvent_t e : ctx->spare_events) (void)hipEventDestroy(e);
+  ctx->spare_events.clear();
 }
 
 extern "C" {

@@ -17,6 +17,26 @@ struct Budget {
   size_t used = 0;
 };
 
+// Freed job arenas kept for later jobs: taking one needs no allocation and,
+// unlike hipFree, no wait for the device.  Pooled bytes stay charged to the
+// budget (the context still holds them) until they are freed: past the cap
+// (largest first), or all at once by trim(), which an allocation that fails
+// calls before it gives up.
+struct Pool {
+  struct Block {
+    char *p;
+    size_t bytes;
+  };
+  std::vector<Block> blocks;
+  size_t bytes = 0;
+  size_t cap = (size_t)32 << 30;  // most bytes kept
+  Budget *budget = nullptr;
+  // the smallest block of need .. need + need / 4 + 1 MiB bytes, or nullptr
+  char *take(size_t need, size_t &got);
+  void give(char *p, size_t n);
+  void trim();
+};
+
 // Growable device buffer carved into 256-byte aligned pieces per call.  A
 // fixed arena uses memory it does not own (the no-allocation entry point's
 // static buffer): it never allocates or frees, and a reserve beyond its
@@ -31,6 +51,7 @@ struct Arena {
   const Arena *after = nullptr; // fixed: start after this arena's carving
   Budget *budget = nullptr;     // charged for what this arena allocates
   bool exact = false;           // allocate exactly what is asked (no growth slack)
+  Pool *pool = nullptr;         // released memory goes here, and reserve looks here first
   hipError_t reserve(size_t bytes);  // resets the carve offset
   void *take(size_t bytes);
   void release();
@@ -156,6 +177,12 @@ struct exz_ctx {
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   // released jobs whose device work had not ended yet; freed once it has
   std::vector<exz_job *> graveyard;
+  exz::Pool job_pool;  // the freed arenas of jobs, for later jobs
+  // the pinned state blocks and events of freed jobs, for later jobs (freeing
+  // pinned memory waits for the device; these are reused instead)
+  std::vector<void *> spare_pinned;
+  std::vector<hipEvent_t> spare_events;
+  static constexpr size_t SPARE_JOBS = 256;
 };
 
 // Frees every job of ctx's graveyard (the device must be idle).

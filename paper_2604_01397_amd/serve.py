@@ -288,9 +288,10 @@ class DeviceExecutor:
         return isinstance(e, self.torch.cuda.OutOfMemoryError)
 
     def reclaim(self):
-        """Returns the caching allocator's free blocks to the device, where
-        the library's allocations can use them."""
+        """Returns the caching allocator's free blocks, and the library's
+        pooled job arenas, to the device."""
         self.torch.cuda.empty_cache()
+        self.ctx.set_option("trim", 1)
 
     def footprint_of(self, spec, result) -> Optional[int]:
         """The job's real footprint once its set-up has run, else None."""

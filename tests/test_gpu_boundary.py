@@ -94,6 +94,10 @@ def test_context_budget():
                 break
         assert torch.equal(job.g_out, ref)
         job.release()
+        # the released workspace is pooled for later jobs (still counted),
+        # and trimming the pool gives it back
+        assert ctx.bytes_in_use() <= budget
+        ctx.set_option("trim", 1)
         assert ctx.bytes_in_use() == before
     finally:
         ctx.close()

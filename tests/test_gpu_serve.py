@@ -229,3 +229,46 @@ def test_query_sees_completion_while_steps_queue_up():
         job.release()
     finally:
         ctx.close()
+
+
+def test_released_job_workspace_is_reused():
+    """A released job's workspace goes to the context's pool; the next job
+    of the same shape takes it (no new device memory) and its result equals
+    exz_correct; "trim" gives the pooled memory back."""
+    from paper_2604_01397_amd import exactz
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx, ref = exactz.Context(0), exactz.Context(0)  # jobs; the plain corrections
+    try:
+        base = ctx.bytes_in_use()
+        cases = [synth.case_grf3d(48, seed=51, rel=1e-3), synth.case_grf3d(48, seed=52, rel=1e-3)]
+        held = []
+        for i, c in enumerate(cases):
+            print("job", i, c.name, flush=True)
+            f = torch.from_numpy(np.ascontiguousarray(c.f)).cuda()
+            g = torch.from_numpy(np.ascontiguousarray(c.g_hat)).cuda()
+            job = ctx.job_create(f, g.clone(), c.xi)
+            for _ in range(200):
+                ctx.step([job], 2)
+                if job.poll()[0]:
+                    break
+            done, r = job.poll()
+            assert done
+            g1, c1, r1 = ref.correct(f, g, c.xi)
+            torch.cuda.synchronize()
+            assert torch.equal(job.g_out, g1) and torch.equal(job.cnt, c1)
+            assert r["iterations"] == r1["iterations"]
+            job.release()
+            torch.cuda.synchronize()
+            held.append(ctx.bytes_in_use())
+            want = exactz.workspace_bytes((48, 48, 48), num_critical=r["num_critical"]) - 48 ** 3
+        # the second job took at least the first one's per-vertex block (same
+        # size) from the pool, so it allocated less than its whole workspace
+        assert held[1] - held[0] < want, (held, want)
+        ctx.set_option("trim", 1)
+        assert ctx.bytes_in_use() < held[1]
+        ctx.set_option("job_pool", 0)  # no pool: a released job frees at once
+        assert ctx.bytes_in_use() == base
+    finally:
+        ctx.close()
+        ref.close()
