@@ -337,6 +337,9 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 96-field batched workload (for profiling) and print its "
                          "figures as one JSON line")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only run the serving trace (--serve-jobs, --serve-rate, "
+                         "--no-serve-plain) and print its figures as one JSON line")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write elementwise kernel 3 times "
                          "(scale for the HBM traffic counters)")
@@ -363,6 +366,12 @@ def main():
 
     if args.batched_only:
         print(json.dumps({"batched": run_batched(torch, exactz, synth)}), flush=True)
+        return
+    if args.serving_only:
+        from paper_2604_01397_amd import serve
+        print(json.dumps({"serving": run_serving(torch, exactz, synth, serve, args.serve_jobs,
+                                                 args.serve_rate, plain=not args.no_serve_plain)}),
+              flush=True)
         return
 
     t0 = time.time()
