@@ -621,6 +621,43 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       layout_b(m.fd, (uint32_t)m.fd.K, L, ob[k]);
       baseB[k] = LB.add(L.total);
     }
+    // The critical points of all members with keys of one width are sorted
+    // together (see SortTile): a few launches per pass for the whole batch
+    // instead of twenty per member.  A group whose counts would not fit 32
+    // bits sorts member by member.
+    struct SortGroup {
+      uint64_t total = 0, tiles = 0;
+      std::vector<SortTile> desc;
+      size_t keys = 0, keys_tmp = 0, vals = 0, vals_tmp = 0, hist = 0, scan = 0, tdesc = 0;
+      bool on = false;
+    } grp[2];
+    std::vector<uint32_t> start(nb, 0);
+    for (size_t k = 0; k < nb; ++k) {
+      const Member &m = mem[k];
+      if (!m.active || m.fd.K <= 0) continue;
+      SortGroup &g = grp[m.fd.dtype == 0 ? 0 : 1];
+      const uint32_t K = (uint32_t)m.fd.K, nt = (K + SORT_TILE - 1) / SORT_TILE;
+      start[k] = (uint32_t)g.total;
+      for (uint32_t t = 0; t < nt; ++t)
+        g.desc.push_back(SortTile{(uint32_t)g.total + t * SORT_TILE,
+                                  std::min(SORT_TILE, K - t * SORT_TILE),
+                                  (uint32_t)(256 * g.tiles), nt, t});
+      g.total += K;
+      g.tiles += nt;
+    }
+    for (int gi = 0; gi < 2; ++gi) {
+      SortGroup &g = grp[gi];
+      const size_t kb = gi == 0 ? 4 : 8;
+      g.on = g.total > 0 && g.total < (1ull << 31) && 256 * g.tiles < (1ull << 31);
+      if (!g.on) continue;
+      g.keys = LB.add(kb * g.total);
+      g.keys_tmp = LB.add(kb * g.total);
+      g.vals = LB.add(4 * g.total);
+      g.vals_tmp = LB.add(4 * g.total);
+      g.hist = LB.add(4 * (256 * g.tiles + 1));
+      g.scan = LB.add(4 * scan_tmp_words((uint32_t)(256 * g.tiles)));
+      g.tdesc = LB.add(sizeof(SortTile) * g.tiles);
+    }
     HIP_OR_FAIL_B(ctx->BB.reserve(LB.total ? LB.total : 256));
     char *Bm = (char *)ctx->BB.take(LB.total);
     HIP_OR_FAIL_B(side_fork(ctx, s));
@@ -637,7 +674,13 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
       fd.cp_vtx = (uint32_t *)(b + ob[k][1]);
       fd.cp_idx = (uint32_t *)(b + ob[k][3]);
       fd.cpr = b + ob[k][4];
-      if (K > 0) {
+      if (K == 0) continue;
+      const SortGroup &g = grp[fd.dtype == 0 ? 0 : 1];
+      if (g.on) {  // into the group's arrays; sorted below
+        const size_t kb = fd.dtype == 0 ? 4 : 8;
+        HIP_OR_FAIL_B(launch_cp_compact(fd, ctx->d_comp, Bm + g.keys + kb * start[k],
+                                        (uint32_t *)(Bm + g.vals) + start[k], sk));
+      } else {
         const size_t hw = radix_hist_words(K);
         HIP_OR_FAIL_B(launch_cp_compact(fd, ctx->d_comp, b + ob[k][5], (uint32_t *)(b + ob[k][7]), sk));
         HIP_OR_FAIL_B(launch_radix_sort(fd.dtype == 0 ? 4 : 8, b + ob[k][5], (uint32_t *)(b + ob[k][7]),
@@ -646,8 +689,32 @@ exz_status exz_correct_batch(exz_ctx *ctx, const exz_field *fields, int32_t nfie
                                         scan_tmp_words((uint32_t)(hw - 1)), sk));
         HIP_OR_FAIL_B(launch_cp_init(fd, (uint32_t *)(b + ob[k][7]), sk));
       }
-      host_fd[k] = fd;
     }
+    if (grp[0].on || grp[1].on) {
+      HIP_OR_FAIL_B(side_join(ctx, s));
+      for (int gi = 0; gi < 2; ++gi) {
+        const SortGroup &g = grp[gi];
+        if (!g.on) continue;
+        HIP_OR_FAIL_B(hipMemcpyAsync(Bm + g.tdesc, g.desc.data(), sizeof(SortTile) * g.tiles,
+                                     hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL_B(launch_radix_sort_tiles(
+            gi == 0 ? 4 : 8, Bm + g.keys, (uint32_t *)(Bm + g.vals), Bm + g.keys_tmp,
+            (uint32_t *)(Bm + g.vals_tmp), (uint32_t)g.total, (const SortTile *)(Bm + g.tdesc),
+            (uint32_t)g.tiles, (uint32_t *)(Bm + g.hist), (uint32_t *)(Bm + g.scan),
+            scan_tmp_words((uint32_t)(256 * g.tiles)), s));
+      }
+      HIP_OR_FAIL_B(side_fork(ctx, s));
+      for (size_t k = 0; k < nb; ++k) {
+        const Member &m = mem[k];
+        if (!m.active || m.fd.K <= 0) continue;
+        const SortGroup &g = grp[m.fd.dtype == 0 ? 0 : 1];
+        if (g.on)
+          HIP_OR_FAIL_B(launch_cp_init(m.fd, (uint32_t *)(Bm + g.vals) + start[k],
+                                       ctx->side[k % exz_ctx::NSIDE]));
+      }
+    }
+    for (size_t k = 0; k < nb; ++k)
+      if (mem[k].active) host_fd[k] = mem[k].fd;
     // original-mode members: path workspace (f's and g's labels, saddle
     // order, f's selections; the certificate's labels too) and its set-up,
     // on the member's side stream after its critical points

@@ -72,6 +72,25 @@ struct Arena {
   }
 };
 
+// One tile of a radix sort over the critical points of several fields at
+// once: the fields' keys lie one after another, every tile within one field,
+// and each field's digit histograms form one block (digit-major over the
+// field's tiles) after those of the fields before it, so one exclusive scan
+// of the concatenated histograms gives every (field, digit, tile) its output
+// position: the sum over the earlier fields is where the field's keys start.
+struct SortTile {
+  uint32_t start;   // first key of the tile
+  uint32_t count;   // keys in the tile (<= 4096)
+  uint32_t hbase;   // first histogram entry of the tile's field
+  uint32_t ntiles;  // tiles of the field
+  uint32_t t;       // the tile's index within its field
+};
+hipError_t launch_radix_sort_tiles(int key_bytes, void *keys, uint32_t *vals, void *keys_tmp,
+                                   uint32_t *vals_tmp, uint32_t count, const SortTile *tiles,
+                                   uint32_t ntiles, uint32_t *hist, uint32_t *scan_tmp,
+                                   size_t scan_words, hipStream_t s);
+constexpr uint32_t SORT_TILE = 4096;  // keys per sort tile
+
 // Size accounting that mirrors Arena::take.
 struct Layout {
   size_t total = 0;

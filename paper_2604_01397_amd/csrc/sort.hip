@@ -9,7 +9,7 @@
 // One pass = per-block digit histograms (digit-major), an exclusive scan of
 // the histograms, and a stable scatter that orders each tile by digit in LDS
 // before writing it out in coalesced runs.
-#include "exz_internal.h"
+#include "exz_host.h"
 
 namespace exz {
 
@@ -18,19 +18,45 @@ constexpr int RS_WAVES = RS_BLOCK / 64;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
 
+static_assert(RS_TILE == SORT_TILE, "sort tiles");
+
+// A work-group's tile: its keys [e0, e0 + n) and where its count of digit d
+// goes in the digit-major histogram (hist[h0 + d * stride]): one sort over
+// all blocks (tiles == nullptr), or the tiles of several fields.
+struct TileOf {
+  uint32_t e0, n, h0, stride;
+};
+__device__ __forceinline__ TileOf tile_of(const SortTile *tiles, uint32_t count, uint32_t nblocks) {
+  TileOf t;
+  if (tiles) {
+    const SortTile d = tiles[blockIdx.x];
+    t.e0 = d.start;
+    t.n = d.count;
+    t.h0 = d.hbase + d.t;
+    t.stride = d.ntiles;
+  } else {
+    t.e0 = blockIdx.x * RS_TILE;
+    t.n = min((uint32_t)RS_TILE, count - t.e0);
+    t.h0 = blockIdx.x;
+    t.stride = nblocks;
+  }
+  return t;
+}
+
 template <class K>
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const K *keys, uint32_t count, int shift,
-                                                      uint32_t *hist, uint32_t nblocks) {
+                                                      uint32_t *hist, uint32_t nblocks,
+                                                      const SortTile *tiles) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const uint32_t base = blockIdx.x * RS_TILE;
+  const TileOf tl = tile_of(tiles, count, nblocks);
   for (int r = 0; r < RS_ITEMS; ++r) {
-    const uint32_t e = base + r * RS_BLOCK + threadIdx.x;
-    if (e < count) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & 255u], 1u);
+    const uint32_t i = r * RS_BLOCK + threadIdx.x;
+    if (i < tl.n) atomicAdd(&h[(uint32_t)(keys[tl.e0 + i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  hist[threadIdx.x * tl.stride + tl.h0] = h[threadIdx.x];
 }
 
 // Stable scatter of one tile of RS_TILE elements.  Wave w owns the tile's
@@ -49,7 +75,8 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const K *keys, uint32_t co
 template <class K>
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uint32_t *vin, K *kout,
                                                          uint32_t *vout, uint32_t count, int shift,
-                                                         const uint32_t *offs, uint32_t nblocks) {
+                                                         const uint32_t *offs, uint32_t nblocks,
+                                                         const SortTile *tiles) {
   __shared__ K sk[RS_TILE];
   __shared__ uint32_t sv[RS_TILE];
   __shared__ uint32_t gbase[256];   // output position of the tile's first element of digit d
@@ -57,8 +84,8 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uin
   __shared__ uint32_t wcnt[RS_WAVES][256];
   __shared__ uint32_t wtot[RS_WAVES];
   const int lane = __lane_id(), w = threadIdx.x >> 6, t = threadIdx.x;
-  const uint32_t b = blockIdx.x;
-  const uint32_t hidx = (uint32_t)t * nblocks + b;
+  const TileOf tl = tile_of(tiles, count, nblocks);
+  const uint32_t hidx = (uint32_t)t * tl.stride + tl.h0;
   const uint32_t g0 = offs[hidx];
   const uint32_t c = offs[hidx + 1] - g0;  // this tile's count of digit t
   gbase[t] = g0;
@@ -66,20 +93,19 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uin
   for (int k = 0; k < RS_WAVES; ++k) wcnt[k][t] = 0;
   __syncthreads();
   const unsigned long long below = (1ull << lane) - 1ull;
-  const uint32_t tile = b * RS_TILE;
-  const uint32_t wbase = tile + (uint32_t)w * (64u * RS_ITEMS);
+  const uint32_t wbase = (uint32_t)w * (64u * RS_ITEMS);  // the wave's first key in the tile
   K key[RS_ITEMS];
   uint32_t val[RS_ITEMS], rk[RS_ITEMS];  // rank within the wave's digit | digit << 16
 #pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
     const uint32_t e = wbase + (uint32_t)r * 64u + (uint32_t)lane;
-    const bool valid = e < count;
+    const bool valid = e < tl.n;
     key[r] = 0;
     val[r] = 0;
     uint32_t d = 0;
     if (valid) {
-      key[r] = kin[e];
-      val[r] = vin[e];
+      key[r] = kin[tl.e0 + e];
+      val[r] = vin[tl.e0 + e];
       d = (uint32_t)(key[r] >> shift) & 255u;
     }
     unsigned long long m = __ballot(valid);
@@ -121,7 +147,7 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uin
 #pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
     const uint32_t e = wbase + (uint32_t)r * 64u + (uint32_t)lane;
-    if (e < count) {
+    if (e < tl.n) {
       const uint32_t d = rk[r] >> 16;
       const uint32_t pos = lstart[d] + wcnt[w][d] + (rk[r] & 0xFFFFu);
       sk[pos] = key[r];
@@ -129,8 +155,7 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const K *kin, const uin
     }
   }
   __syncthreads();
-  const uint32_t n_tile = min((uint32_t)RS_TILE, count - tile);
-  for (uint32_t j = t; j < n_tile; j += RS_BLOCK) {
+  for (uint32_t j = t; j < tl.n; j += RS_BLOCK) {
     const K k = sk[j];
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
     const uint32_t pos = gbase[d] + (j - lstart[d]);
@@ -153,16 +178,53 @@ static hipError_t sort_impl(K *keys, uint32_t *vals, K *ktmp, uint32_t *vtmp, ui
   uint32_t *va = vals, *vb = vtmp;
   for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += 8) {
     hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_BLOCK), 0, s, ka, count, shift, hist,
-                       nblocks);
+                       nblocks, (const SortTile *)nullptr);
     hipError_t e = launch_scan_u32(hist, hist, 256u * nblocks, scan_tmp, scan_words, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rs_scatter<K>, dim3(nblocks), dim3(RS_BLOCK), 0, s, ka, va, kb, vb, count,
-                       shift, hist, nblocks);
+                       shift, hist, nblocks, (const SortTile *)nullptr);
     K *kt = ka; ka = kb; kb = kt;
     uint32_t *vt = va; va = vb; vb = vt;
   }
   // an even number of passes leaves the result in (keys, vals)
   return hipGetLastError();
+}
+
+// The same passes over the tiles of several fields' keys (see SortTile): one
+// histogram and one scatter launch per pass for all of them.
+template <class K>
+static hipError_t sort_tiles_impl(K *keys, uint32_t *vals, K *ktmp, uint32_t *vtmp, uint32_t count,
+                                  const SortTile *tiles, uint32_t ntiles, uint32_t *hist,
+                                  uint32_t *scan_tmp, size_t scan_words, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  K *ka = keys, *kb = ktmp;
+  uint32_t *va = vals, *vb = vtmp;
+  for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist<K>, dim3(ntiles), dim3(RS_BLOCK), 0, s, ka, count, shift, hist,
+                       ntiles, tiles);
+    hipError_t e = launch_scan_u32(hist, hist, 256u * ntiles, scan_tmp, scan_words, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rs_scatter<K>, dim3(ntiles), dim3(RS_BLOCK), 0, s, ka, va, kb, vb, count,
+                       shift, hist, ntiles, tiles);
+    K *kt = ka; ka = kb; kb = kt;
+    uint32_t *vt = va; va = vb; vb = vt;
+  }
+  // an even number of passes leaves the result in (keys, vals)
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_sort_tiles(int key_bytes, void *keys, uint32_t *vals, void *keys_tmp,
+                                   uint32_t *vals_tmp, uint32_t count, const SortTile *tiles,
+                                   uint32_t ntiles, uint32_t *hist, uint32_t *scan_tmp,
+                                   size_t scan_words, hipStream_t s) {
+  if (key_bytes == 4)
+    return sort_tiles_impl<uint32_t>((uint32_t *)keys, vals, (uint32_t *)keys_tmp, vals_tmp, count,
+                                     tiles, ntiles, hist, scan_tmp, scan_words, s);
+  if (key_bytes == 8)
+    return sort_tiles_impl<unsigned long long>((unsigned long long *)keys, vals,
+                                               (unsigned long long *)keys_tmp, vals_tmp, count,
+                                               tiles, ntiles, hist, scan_tmp, scan_words, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_radix_sort(int key_bytes, void *keys, uint32_t *vals, void *keys_tmp,
