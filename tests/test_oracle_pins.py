@@ -244,11 +244,12 @@ def _check_certificates(f, g, xi, g_out, cnt, st, N, mode):
     return True
 
 
-@pytest.mark.parametrize("mode", [oracle.REFORMULATED, oracle.ORIGINAL])
-@pytest.mark.parametrize("shape", SHAPES)
+# 1D fields have no saddles, so the original event constraints (C2, C3) say
+# nothing there: the original mode is certified on 2D and 3D shapes only.
+@pytest.mark.parametrize("shape,mode", [(s, m) for m in (oracle.REFORMULATED, oracle.ORIGINAL)
+                                        for s in SHAPES
+                                        if not (m == oracle.ORIGINAL and len(s) == 1)])
 def test_random_tiny_certificates(shape, mode):
-    if mode == oracle.ORIGINAL and len(shape) == 1:
-        pytest.skip("1D has no saddles: the original event constraints are vacuous")
     rng = np.random.default_rng(hash((shape, mode)) % 2 ** 32)
     converged = 0
     for trial in range(8):
