@@ -157,8 +157,9 @@ exz_status exz_ctx_destroy(exz_ctx *ctx);
  *   "job_pool" bytes of released jobs' workspace the context keeps for
  *              later jobs (default 32 GiB; 0 frees each at once).  Taking
  *              pooled memory needs no allocation and freeing into the pool
- *              no wait for the device; pooled bytes count as in use, and
- *              an allocation that fails frees the pool and tries again;
+ *              no wait for the device; pooled bytes count as in use.  A
+ *              job whose workspace would pass the context's budget, or whose
+ *              allocation fails, frees the pool first (then tries again);
  *   "trim"     frees the pooled job workspace now (value ignored).
  * Returns EXZ_E_INVALID for an unknown key or value. */
 exz_status exz_ctx_set_option(exz_ctx *ctx, const char *key, int64_t value);
