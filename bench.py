@@ -222,7 +222,7 @@ def run_float64(torch, exactz, synth, edge=512, reps=3):
             "residual_violations": res["residual_violations"]}
 
 
-def run_serving(torch, exactz, synth, serve, jobs, rate, plain=True):
+def run_serving(torch, exactz, synth, serve, jobs, rate, plain=True, max_active=16):
     """Continuous-batching server on a Poisson trace of (L+2)^3 float32 blocks,
     then (same jobs, same inputs) plain per-field exz_correct one after the
     other."""
@@ -274,7 +274,7 @@ def run_serving(torch, exactz, synth, serve, jobs, rate, plain=True):
     budget = int(0.8 * free)
     ctx = exactz.Context(0)
     ex = serve.DeviceExecutor(ctx, tuned=True)
-    rep = serve.Server(ex, budget, max_active=64, iters_per_step=4,
+    rep = serve.Server(ex, budget, max_active=max_active, iters_per_step=4,
                        progress=lambda d: log("serving: %s" % d)).run(specs)
     torch.cuda.synchronize()
     out = rep.summary()
@@ -332,6 +332,8 @@ def main():
                     help="skip the batched and serving measurements")
     ap.add_argument("--serve-jobs", type=int, default=1000, help="jobs in the serving trace")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--serve-max-active", type=int, default=16,
+                    help="most jobs the server keeps active at once")
     ap.add_argument("--no-serve-plain", action="store_true",
                     help="skip the plain per-field run of the serving jobs")
     ap.add_argument("--batched-only", action="store_true",
@@ -370,7 +372,8 @@ def main():
     if args.serving_only:
         from paper_2604_01397_amd import serve
         print(json.dumps({"serving": run_serving(torch, exactz, synth, serve, args.serve_jobs,
-                                                 args.serve_rate, plain=not args.no_serve_plain)}),
+                                                 args.serve_rate, plain=not args.no_serve_plain,
+                                                 max_active=args.serve_max_active)}),
               flush=True)
         return
 
@@ -476,7 +479,8 @@ def main():
         log("float64: %s" % line["float64"])
         torch.cuda.empty_cache()
         line["serving"] = run_serving(torch, exactz, synth, serve, args.serve_jobs, args.serve_rate,
-                                      plain=not args.no_serve_plain)
+                                      plain=not args.no_serve_plain,
+                                      max_active=args.serve_max_active)
         log("serving: %s" % line["serving"])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sub-block ...")
